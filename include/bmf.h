@@ -1,0 +1,249 @@
+/*
+ * bmf.h -- C ABI of libbmf: block-based biased-SVD matrix factorisation
+ * trained by stratified block-parallel SGD on one AMD MI355X (gfx950).
+ *
+ * Method: Bhavana, Kumar, Padmanabhan, "Block based Singular Value
+ * Decomposition approach to matrix factorization for recommender systems"
+ * (arXiv 1907.07410).  X is an m x n rating matrix, m users (rows) and n
+ * items (columns) (Section 3, Algorithm 1's inputs); U = P (m x k) and
+ * V = Q (n x k) are the latent factors, bu (m) and bi (n) the biases
+ * (Algorithm 1; Eq 3); the prediction is mu + bu_u + bi_i + p_u . q_i.
+ *
+ * Conventions for every call:
+ *  - Every call returns bmf_status: 0 on success, a negative code on error.
+ *    No C++ exception crosses this boundary.  bmf_last_error(ctx) returns a
+ *    message for the last failed call on ctx (bmf_last_error(NULL): the last
+ *    failed create on this thread).
+ *  - Validation errors (BMF_E_INVAL, BMF_E_RANGE, BMF_E_STATE, BMF_E_NOMEM)
+ *    leave the context exactly as it was.  BMF_E_DEVICE (a HIP runtime error)
+ *    poisons the context: afterwards only bmf_get_factors, bmf_last_error
+ *    and bmf_destroy are accepted.
+ *  - Host pointers (plain names) are read or written before the call
+ *    returns; the library never keeps them.  Output buffers are allocated by
+ *    the caller with the documented sizes.  "_dev" calls take device
+ *    pointers on the context's device and only enqueue work on the
+ *    context's stream (BMF_OPT_STREAM): they return before the GPU is done.
+ *  - The context owns all device memory it allocates.  A context is used by
+ *    one host thread at a time; distinct contexts are independent.
+ *  - Factor tables are FP32, row-major: P[u*k + f], Q[i*k + f].  Reductions
+ *    that report RMSE or loss accumulate in FP64.
+ */
+#ifndef BMF_H
+#define BMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bmf_ctx bmf_ctx;
+typedef struct bmf_batch bmf_batch;
+typedef struct bmf_server bmf_server;
+
+typedef enum {
+    BMF_OK = 0,
+    BMF_E_INVAL = -1,  /* bad argument (null pointer, size <= 0, bad option) */
+    BMF_E_RANGE = -2,  /* an index or value outside its domain */
+    BMF_E_STATE = -3,  /* call not allowed in the current state */
+    BMF_E_NOMEM = -4,  /* device or host allocation failed / budget exceeded */
+    BMF_E_DEVICE = -5  /* HIP runtime error; the context is poisoned */
+} bmf_status;
+
+typedef enum {
+    /* seed of the initial factors, default 1001.  Setting it re-draws P and
+     * Q (Algorithm 1 initialises them "with random values"): entry (row, f)
+     * of tensor T (1 = P, 2 = Q) is 0.125 * (2 * (x >> 40) * 2^-24 - 1),
+     * x = SplitMix64 draw number row*k + f of the stream seed ^ (T << 56);
+     * biases start at 0. */
+    BMF_OPT_SEED = 0,
+    /* seed of the per-epoch stratum order (mode 1), default 2001 */
+    BMF_OPT_ORDER_SEED = 1,
+    /* 0: strata 0, 1, ..., b-1 every epoch (Section 3: the diagonal first,
+     *    then the blocks below it, columns wrapping);
+     * 1: a Fisher-Yates shuffle of 0..b-1 per epoch e drawn from the
+     *    SplitMix64 stream order_seed ^ (3 << 56) ^ (e << 24)
+     *    (for t = b-1..1: j = draw(b-1-t) mod (t+1), swap t and j).
+     * Default 0. */
+    BMF_OPT_STRATUM_ORDER = 2,
+    /* 0: mu = FP64 mean of the training ratings (default);
+     * 1: mu = 0 (Eq 3 taken literally). Takes effect at the next load. */
+    BMF_OPT_MU_MODE = 3,
+    /* hipStream_t (cast to int64) on which all work is enqueued; 0 = the
+     * context's own stream. */
+    BMF_OPT_STREAM = 4,
+    /* SGD kernel: 0 = automatic, 1 = global-memory reference kernel,
+     * 2 = LDS-staged item slice kernel.  All produce the same update
+     * sequence; the value only changes speed. */
+    BMF_OPT_SGD_KERNEL = 5,
+    /* stratum synchronisation: 0 = one launch per stratum (default),
+     * 1 = one persistent launch per epoch with per-row and per-column
+     * progress counters (falls back to 0 when the grid cannot be
+     * co-resident). */
+    BMF_OPT_PERSISTENT = 6
+} bmf_option;
+
+/* ------------------------------------------------------------- lifetime */
+
+/* Create a model for m users, n items, k latent factors and a b x b block
+ * grid (Algorithm 1, steps 1-2; Section 3's block representation).  Blocks
+ * have rb = ceil(m/b) rows and cb = ceil(n/b) columns; the last block row or
+ * column may be short or empty.  Allocates P, Q, bu, bi on the current HIP
+ * device and draws P and Q as described under BMF_OPT_SEED.
+ * Errors: BMF_E_INVAL if out == NULL or m, n, k, b < 1 or k > 1024;
+ * BMF_E_NOMEM; BMF_E_DEVICE. */
+bmf_status bmf_create(int64_t m, int64_t n, int32_t k, int32_t b, bmf_ctx **out);
+
+/* Set an option (bmf_option).  Errors: BMF_E_INVAL for an unknown key or a
+ * value outside the documented set. */
+bmf_status bmf_set_option(bmf_ctx *c, int32_t key, int64_t value);
+
+/* Release everything the context owns.  c may be NULL. */
+void bmf_destroy(bmf_ctx *c);
+
+/* Message for the last failed call on c (c == NULL: last failed create on
+ * this thread).  Valid until the next call on c. */
+const char *bmf_last_error(const bmf_ctx *c);
+
+/* Wait for all work enqueued on the context's stream. */
+bmf_status bmf_synchronize(bmf_ctx *c);
+
+/* ------------------------------------------------------------- training */
+
+/* Load the training ratings as COO triples (u[t], i[t], r[t]), t < nnz,
+ * copied from host memory.  Every triple is an observation (ratings <= 0
+ * included); duplicates are separate observations.  Checks 0 <= u < m,
+ * 0 <= i < n and finite r (BMF_E_RANGE names the first bad index), computes
+ * mu, and partitions the ratings into the b x b blocks on the device: block
+ * (u / rb, i / cb), visited inside a block in (u, i, t) order (Algorithm 2's
+ * row and column loops).  Replaces previously loaded ratings; keeps the
+ * factors.  nnz may be 0 (then u, i, r may be NULL).
+ * Errors: BMF_E_INVAL, BMF_E_RANGE (also when a block's local (row, column)
+ * needs more than 32 bits: use a larger b), BMF_E_NOMEM, BMF_E_DEVICE. */
+bmf_status bmf_load_ratings(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r,
+                            int64_t nnz);
+
+/* Same with device pointers (int32 u, int32 i, float r on the context's
+ * device).  Synchronises the stream before returning. */
+bmf_status bmf_load_ratings_dev(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r,
+                                int64_t nnz);
+
+/* One epoch (one iteration of Algorithm 1's loop): the b strata in this
+ * epoch's order (BMF_OPT_STRATUM_ORDER); within a stratum s the b blocks
+ * ((j + s) mod b, j), which share no user and no item, run concurrently;
+ * every training rating is visited exactly once (Section 3).  Per rating
+ * (Eqs 10-13 with one residual taken before any update):
+ *   err  = r - mu - bu_u - bi_i - p_u . q_i
+ *   bu_u += lr (err - reg bu_u);  bi_i += lr (err - reg bi_i)
+ *   p_u  += lr (err q_i - reg p_u);  q_i += lr (err p_u - reg q_i)
+ * with p_u and q_i on the right-hand sides taken before the update.
+ * Enqueued on the context's stream; returns without waiting.
+ * Errors: BMF_E_STATE before a load; BMF_E_DEVICE. */
+bmf_status bmf_epoch(bmf_ctx *c, float lr, float reg);
+
+/* Same with the four (alpha, beta) pairs of Eqs 10-13 given by name:
+ * hp = {alpha_p, beta_p, alpha_q, beta_q, alpha_bu, beta_bu, alpha_bi,
+ * beta_bi} (user latent, item latent, user bias, item bias). */
+bmf_status bmf_epoch_hp(bmf_ctx *c, const float hp[8]);
+
+/* Number of epochs run so far (the next epoch's index). */
+bmf_status bmf_epoch_count(const bmf_ctx *c, int32_t *out);
+
+/* Order of the strata of epoch `epoch` (b entries). */
+bmf_status bmf_get_schedule(const bmf_ctx *c, int32_t epoch, int32_t *order);
+
+/* The partition of the loaded ratings: block_ptr[b*b + 1] (bucket offsets,
+ * block id = row * b + column) and perm[nnz] (perm[pos] = input index of
+ * the rating visited at position pos). */
+bmf_status bmf_get_partition(bmf_ctx *c, int64_t *block_ptr, int32_t *perm);
+
+/* Copy the model out (any pointer may be NULL to skip it).  P: m*k, Q: n*k,
+ * bu: m, bi: n floats; mu: one double.  Waits for the stream. */
+bmf_status bmf_get_factors(bmf_ctx *c, float *P, float *Q, float *bu, float *bi, double *mu);
+
+/* Replace the model (any pointer may be NULL to keep that part). */
+bmf_status bmf_set_factors(bmf_ctx *c, const float *P, const float *Q, const float *bu,
+                           const float *bi, const double *mu);
+
+/* Device pointers to the live FP32 tables (owned by the context). */
+bmf_status bmf_factor_ptrs(bmf_ctx *c, float **P, float **Q, float **bu, float **bi);
+
+/* ----------------------------------------------------------- evaluation */
+
+/* RMSE = sqrt(mean((r - (mu + bu_u + bi_i + p_u . q_i))^2)) over the given
+ * ratings (host COO, cnt entries), or over the training ratings when u is
+ * NULL.  Residuals in FP32, squares summed in FP64 in a fixed order (the
+ * result does not depend on launch timing).  Algorithm 1's stopping test
+ * uses the RMSE; the paper reports test RMSE (Section 5, Table 1).
+ * Errors: BMF_E_RANGE for an out-of-range index; BMF_E_STATE. */
+bmf_status bmf_rmse(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r, int64_t cnt,
+                    double *out);
+
+/* Regularised loss over the training ratings: sum of err^2 + beta_p |p_u|^2
+ * + beta_q |q_i|^2 + beta_bu bu_u^2 + beta_bi bi_i^2 at every rating (Eq 9
+ * with the penalty charged per observed rating, the objective per-rating SGD
+ * descends).  hp as in bmf_epoch_hp (only the betas are used). */
+bmf_status bmf_loss(bmf_ctx *c, const float hp[8], double *out);
+
+/* ---------------------------------------------------------------- top-K */
+
+/* For each of the nu user ids, the K items with the largest predicted
+ * rating over all n items, best first, ties to the smaller item id.
+ * Scores use FP32 factors on FP32 MFMA (v_mfma_f32_16x16x4_f32) with a
+ * fixed accumulation order, so a user's result does not depend on the other
+ * users in the call.  items_out[nu*K] (int32), scores_out[nu*K] (float,
+ * the predicted rating mu + bu_u + bi_i + p_u . q_i).  If K > n the tail is
+ * item -1 / score -inf.  1 <= K <= 1024.
+ * Errors: BMF_E_INVAL, BMF_E_RANGE (user id), BMF_E_DEVICE. */
+bmf_status bmf_topk(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t *items_out,
+                    float *scores_out);
+
+/* Same ranking with BF16 copies of P and Q on BF16 MFMA (FP32 accumulate)
+ * to pick Kc >= K candidates per user, then an FP32 rescore of those
+ * candidates (fixed-order FP32 dot products) and a final exact top-K of the
+ * rescored values.  The BF16 copies (round to nearest even) are made once
+ * after the factors last changed.  Kc = 0 selects 2K. */
+bmf_status bmf_topk_bf16(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t Kc,
+                         int32_t *items_out, float *scores_out);
+
+/* Device-pointer forms (users, items_out, scores_out on the device);
+ * enqueue only. precision: 0 = FP32 MFMA, 1 = BF16 + FP32 rescore. */
+bmf_status bmf_topk_dev(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t precision,
+                        int32_t Kc, int32_t *items_out, float *scores_out);
+
+/* ---------------------------------------------------------------- fold-in */
+
+/* Fold in a new user (Section 2.1's folding-in of new data; Section 6's
+ * incremental use): item factors and item biases stay fixed, p = 0 and
+ * bu = 0, then `passes` passes over the user's nr ratings in input order,
+ * each applying err = r - mu - bu - bi_i - p . q_i; bu += lr (err - reg bu);
+ * p += lr (err q_i - reg p).  p_out[k], bu_out[1] on the host.
+ * Errors: BMF_E_INVAL, BMF_E_RANGE (item id or non-finite rating). */
+bmf_status bmf_foldin(bmf_ctx *c, const int32_t *items, const float *r, int32_t nr, int32_t passes,
+                      float lr, float reg, float *p_out, float *bu_out);
+
+/* ------------------------------------------------------------- counters */
+
+/* Time spent in SGD kernels since the last reset, measured with HIP events
+ * on the context's stream around each epoch's launches (milliseconds), and
+ * the number of SGD kernel launches. */
+bmf_status bmf_sgd_timing(bmf_ctx *c, double *ms, int64_t *launches, int32_t reset);
+
+/* Stratum order of epoch `epoch` for a b x b grid without a context: the
+ * same rule as BMF_OPT_STRATUM_ORDER (mode 0 identity, mode 1 seeded
+ * Fisher-Yates).  Host-only; order[b].  Errors: BMF_E_INVAL. */
+bmf_status bmf_stratum_order(int32_t b, uint64_t seed, int32_t epoch, int32_t mode, int32_t *order);
+
+/* ---------------------------------------------------------- diagnostics */
+
+/* Reduction self-check on the current device: out[0:64], out[64:128] and
+ * out[128:192] receive, per lane, the 64-lane sum of in[0:64] by the
+ * shuffle butterfly and by the DPP butterfly (both must be identical), and
+ * the 16-lane row sums by DPP.  Host arrays. */
+bmf_status bmf_debug_wave_sum(const float *in64, float *out192);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BMF_H */

@@ -1,0 +1,251 @@
+"""ctypes binding of libbmf (include/bmf.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+The library must have been built (``python -m paper_1907_07410_amd.build``);
+importing this module without it raises.  Host arrays are numpy arrays;
+device arrays are torch tensors on the context's device (``*_dev`` calls).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbmf.so")
+
+BMF_OK, BMF_E_INVAL, BMF_E_RANGE, BMF_E_STATE, BMF_E_NOMEM, BMF_E_DEVICE = 0, -1, -2, -3, -4, -5
+OPT_SEED, OPT_ORDER_SEED, OPT_STRATUM_ORDER, OPT_MU_MODE, OPT_STREAM, OPT_SGD_KERNEL, OPT_PERSISTENT = range(7)
+
+_STATUS = {0: "BMF_OK", -1: "BMF_E_INVAL", -2: "BMF_E_RANGE", -3: "BMF_E_STATE", -4: "BMF_E_NOMEM",
+           -5: "BMF_E_DEVICE"}
+
+
+class BmfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libbmf.so not built at {LIB_PATH}; run python -m paper_1907_07410_amd.build")
+    L = C.CDLL(LIB_PATH)
+    i64, i32, f32, dbl, p = C.c_int64, C.c_int32, C.c_float, C.c_double, C.c_void_p
+    pp = C.POINTER(C.c_void_p)
+    sig = {
+        "bmf_create": ([i64, i64, i32, i32, pp], i32),
+        "bmf_set_option": ([p, i32, i64], i32),
+        "bmf_destroy": ([p], None),
+        "bmf_last_error": ([p], C.c_char_p),
+        "bmf_synchronize": ([p], i32),
+        "bmf_load_ratings": ([p, p, p, p, i64], i32),
+        "bmf_load_ratings_dev": ([p, p, p, p, i64], i32),
+        "bmf_epoch": ([p, f32, f32], i32),
+        "bmf_epoch_hp": ([p, p], i32),
+        "bmf_epoch_count": ([p, p], i32),
+        "bmf_get_schedule": ([p, i32, p], i32),
+        "bmf_get_partition": ([p, p, p], i32),
+        "bmf_get_factors": ([p, p, p, p, p, p], i32),
+        "bmf_set_factors": ([p, p, p, p, p, p], i32),
+        "bmf_factor_ptrs": ([p, pp, pp, pp, pp], i32),
+        "bmf_rmse": ([p, p, p, p, i64, p], i32),
+        "bmf_loss": ([p, p, p], i32),
+        "bmf_topk": ([p, p, i64, i32, p, p], i32),
+        "bmf_topk_bf16": ([p, p, i64, i32, i32, p, p], i32),
+        "bmf_topk_dev": ([p, p, i64, i32, i32, i32, p, p], i32),
+        "bmf_foldin": ([p, p, p, i32, i32, f32, f32, p, p], i32),
+        "bmf_sgd_timing": ([p, p, p, i32], i32),
+        "bmf_debug_wave_sum": ([p, p], i32),
+        "bmf_stratum_order": ([i32, C.c_uint64, i32, i32, p], i32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+lib = _load()
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dptr(t) -> int:
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+class Model:
+    """One bmf context: m users, n items, k factors, b x b blocks."""
+
+    def __init__(self, m: int, n: int, k: int, b: int, seed: Optional[int] = None,
+                 order_mode: Optional[int] = None, order_seed: Optional[int] = None,
+                 mu_mode: Optional[int] = None, sgd_kernel: Optional[int] = None):
+        h = C.c_void_p()
+        st = lib.bmf_create(m, n, k, b, C.byref(h))
+        if st != 0:
+            raise BmfError(st, lib.bmf_last_error(None).decode())
+        self._h = h
+        self.m, self.n, self.k, self.b = m, n, k, b
+        if seed is not None:
+            self.set_option(OPT_SEED, seed)
+        if order_mode is not None:
+            self.set_option(OPT_STRATUM_ORDER, order_mode)
+        if order_seed is not None:
+            self.set_option(OPT_ORDER_SEED, order_seed)
+        if mu_mode is not None:
+            self.set_option(OPT_MU_MODE, mu_mode)
+        if sgd_kernel is not None:
+            self.set_option(OPT_SGD_KERNEL, sgd_kernel)
+
+    # -- plumbing
+    def _check(self, st: int):
+        if st != 0:
+            raise BmfError(st, lib.bmf_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.bmf_destroy(self._h)
+            self._h = None
+
+    destroy = close
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- calls (names follow bmf_*)
+    def set_option(self, key: int, value: int):
+        self._check(lib.bmf_set_option(self._h, key, int(value)))
+
+    def synchronize(self):
+        self._check(lib.bmf_synchronize(self._h))
+
+    def load_ratings(self, u, i, r):
+        u, i, r = _c(u, np.int32), _c(i, np.int32), _c(r, np.float32)
+        self._check(lib.bmf_load_ratings(self._h, _ptr(u), _ptr(i), _ptr(r), u.shape[0]))
+
+    def load_ratings_dev(self, u, i, r):
+        self._check(lib.bmf_load_ratings_dev(self._h, _dptr(u), _dptr(i), _dptr(r), int(u.numel())))
+
+    def epoch(self, lr: float, reg: float):
+        self._check(lib.bmf_epoch(self._h, lr, reg))
+
+    def epoch_hp(self, hp: Sequence[float]):
+        hp = _c(hp, np.float32)
+        self._check(lib.bmf_epoch_hp(self._h, _ptr(hp)))
+
+    def epoch_count(self) -> int:
+        out = C.c_int32()
+        self._check(lib.bmf_epoch_count(self._h, C.byref(out)))
+        return out.value
+
+    def get_schedule(self, epoch: int) -> np.ndarray:
+        out = np.zeros(self.b, dtype=np.int32)
+        self._check(lib.bmf_get_schedule(self._h, epoch, _ptr(out)))
+        return out
+
+    def get_partition(self, nnz: int):
+        bp = np.zeros(self.b * self.b + 1, dtype=np.int64)
+        perm = np.zeros(nnz, dtype=np.int32)
+        self._check(lib.bmf_get_partition(self._h, _ptr(bp), _ptr(perm)))
+        return bp, perm
+
+    def get_factors(self):
+        P = np.zeros((self.m, self.k), dtype=np.float32)
+        Q = np.zeros((self.n, self.k), dtype=np.float32)
+        bu = np.zeros(self.m, dtype=np.float32)
+        bi = np.zeros(self.n, dtype=np.float32)
+        mu = C.c_double()
+        self._check(lib.bmf_get_factors(self._h, _ptr(P), _ptr(Q), _ptr(bu), _ptr(bi), C.byref(mu)))
+        return P, Q, bu, bi, mu.value
+
+    def set_factors(self, P=None, Q=None, bu=None, bi=None, mu=None):
+        args = [None if a is None else _c(a, np.float32) for a in (P, Q, bu, bi)]
+        mu_c = None if mu is None else C.byref(C.c_double(float(mu)))
+        self._check(lib.bmf_set_factors(self._h, *[_ptr(a) for a in args], mu_c))
+
+    def factor_ptrs(self):
+        ps = [C.c_void_p() for _ in range(4)]
+        self._check(lib.bmf_factor_ptrs(self._h, *[C.byref(x) for x in ps]))
+        return [x.value for x in ps]
+
+    def rmse(self, u=None, i=None, r=None) -> float:
+        out = C.c_double()
+        if u is None:
+            self._check(lib.bmf_rmse(self._h, None, None, None, 0, C.byref(out)))
+        else:
+            u, i, r = _c(u, np.int32), _c(i, np.int32), _c(r, np.float32)
+            self._check(lib.bmf_rmse(self._h, _ptr(u), _ptr(i), _ptr(r), u.shape[0], C.byref(out)))
+        return out.value
+
+    def loss(self, lr: float = 0.0, reg: float = 0.0, hp=None) -> float:
+        hp = _c([lr, reg] * 4 if hp is None else hp, np.float32)
+        out = C.c_double()
+        self._check(lib.bmf_loss(self._h, _ptr(hp), C.byref(out)))
+        return out.value
+
+    def topk(self, users, K: int):
+        users = _c(users, np.int32)
+        items = np.zeros((users.shape[0], K), dtype=np.int32)
+        scores = np.zeros((users.shape[0], K), dtype=np.float32)
+        self._check(lib.bmf_topk(self._h, _ptr(users), users.shape[0], K, _ptr(items), _ptr(scores)))
+        return items, scores
+
+    def topk_bf16(self, users, K: int, Kc: int = 0):
+        users = _c(users, np.int32)
+        items = np.zeros((users.shape[0], K), dtype=np.int32)
+        scores = np.zeros((users.shape[0], K), dtype=np.float32)
+        self._check(lib.bmf_topk_bf16(self._h, _ptr(users), users.shape[0], K, Kc, _ptr(items), _ptr(scores)))
+        return items, scores
+
+    def topk_dev(self, users, K: int, precision: int, Kc: int, items_out, scores_out):
+        self._check(lib.bmf_topk_dev(self._h, _dptr(users), int(users.numel()), K, precision, Kc,
+                                     _dptr(items_out), _dptr(scores_out)))
+
+    def foldin(self, items, r, passes: int, lr: float, reg: float):
+        items, r = _c(items, np.int32), _c(r, np.float32)
+        p = np.zeros(self.k, dtype=np.float32)
+        bu = np.zeros(1, dtype=np.float32)
+        self._check(lib.bmf_foldin(self._h, _ptr(items), _ptr(r), items.shape[0], passes, lr, reg, _ptr(p),
+                                   _ptr(bu)))
+        return p, float(bu[0])
+
+    def sgd_timing(self, reset: bool = False):
+        ms = C.c_double()
+        launches = C.c_int64()
+        self._check(lib.bmf_sgd_timing(self._h, C.byref(ms), C.byref(launches), int(reset)))
+        return ms.value, launches.value
+
+
+def stratum_order(b: int, seed: int, epoch: int, mode: int) -> np.ndarray:
+    out = np.zeros(b, dtype=np.int32)
+    st = lib.bmf_stratum_order(b, seed, epoch, mode, _ptr(out))
+    if st != 0:
+        raise BmfError(st, "bmf_stratum_order")
+    return out
+
+
+def debug_wave_sum(x) -> np.ndarray:
+    x = _c(x, np.float32)
+    out = np.zeros(192, dtype=np.float32)
+    st = lib.bmf_debug_wave_sum(_ptr(x), _ptr(out))
+    if st != 0:
+        raise BmfError(st, lib.bmf_last_error(None).decode())
+    return out.reshape(3, 64)

@@ -1,0 +1,445 @@
+// The C ABI (include/bmf.h): argument checks, context state, and the
+// sequencing of the device work.  Every entry point converts internal
+// errors into bmf_status codes; no exception crosses the boundary.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "internal.h"
+
+using namespace bmf;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+template <class F>
+bmf_status guarded(bmf_ctx *c, bool allow_poisoned, F &&f) {
+    if (!c) return BMF_E_INVAL;
+    if (c->poisoned && !allow_poisoned) {
+        c->err = "context is poisoned by an earlier device error";
+        return BMF_E_STATE;
+    }
+    try {
+        BMF_HIP(hipSetDevice(c->M.device));
+        f();
+        return BMF_OK;
+    } catch (const Error &e) {
+        c->err = e.msg;
+        if (e.code == BMF_E_DEVICE) c->poisoned = true;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        c->err = "host allocation failed";
+        return BMF_E_NOMEM;
+    } catch (...) {
+        c->err = "unexpected internal exception";
+        c->poisoned = true;
+        return BMF_E_DEVICE;
+    }
+}
+
+HP hp_from(const float *h) { return HP{h[0], h[1], h[2], h[3], h[4], h[5], h[6], h[7]}; }
+HP hp_uniform(float lr, float reg) { return HP{lr, reg, lr, reg, lr, reg, lr, reg}; }
+
+void init_model_factors(Model &M) {
+    launch_init_factors(M.P.as<float>(), M.m, M.k, M.seed, 1, M.stream);
+    launch_init_factors(M.Q.as<float>(), M.n, M.k, M.seed, 2, M.stream);
+    launch_fill(M.bu.as<float>(), M.m, 0.f, M.stream);
+    launch_fill(M.bi.as<float>(), M.n, 0.f, M.stream);
+    M.bf16_valid = false;
+}
+
+template <class T>
+void upload(DevBuf &dst, const T *src, int64_t cnt, hipStream_t s) {
+    dst.alloc((size_t)cnt * sizeof(T));
+    if (cnt) BMF_HIP(hipMemcpyAsync(dst.p, src, (size_t)cnt * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+void check_finite_hp(const float *hp) {
+    for (int q = 0; q < 8; ++q)
+        if (!std::isfinite(hp[q])) BMF_FAIL(BMF_E_INVAL, "non-finite hyper-parameter");
+}
+
+void load_common(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r, int64_t nnz, bool dev) {
+    Model &M = c->M;
+    if (nnz < 0) BMF_FAIL(BMF_E_INVAL, "nnz < 0");
+    if (nnz > 0 && (!u || !i || !r)) BMF_FAIL(BMF_E_INVAL, "null rating array");
+    if (nnz >= (int64_t)INT32_MAX) BMF_FAIL(BMF_E_INVAL, "nnz must be below 2^31");
+    DevBuf du, di, dr;
+    du.alloc((size_t)nnz * 4);
+    di.alloc((size_t)nnz * 4);
+    dr.alloc((size_t)nnz * 4);
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (nnz) {
+        BMF_HIP(hipMemcpyAsync(du.p, u, nnz * 4, kind, M.stream));
+        BMF_HIP(hipMemcpyAsync(di.p, i, nnz * 4, kind, M.stream));
+        BMF_HIP(hipMemcpyAsync(dr.p, r, nnz * 4, kind, M.stream));
+    }
+    const int64_t bad = validate_coo(du.as<int32_t>(), di.as<int32_t>(), dr.as<float>(), nnz, M.m, M.n, M.red,
+                                     M.stream);
+    if (bad >= 0) {
+        std::string what = "rating " + std::to_string(bad) + " is out of range or not finite";
+        if (!dev) what += " (u=" + std::to_string(u[bad]) + ", i=" + std::to_string(i[bad]) + ")";
+        BMF_FAIL(BMF_E_RANGE, what);
+    }
+    double mu = 0.0;
+    if (M.mu_mode == 0 && nnz > 0) mu = sum_f32_as_f64(dr.as<float>(), nnz, M.red, M.stream) / (double)nnz;
+    Partition P;
+    build_partition(P, du.as<int32_t>(), di.as<int32_t>(), dr.as<float>(), nnz, M.m, M.n, M.b, M.stream);
+    // commit
+    M.cu.swap(du);
+    M.ci.swap(di);
+    M.cr.swap(dr);
+    M.part.recs.swap(P.recs);
+    M.part.perm.swap(P.perm);
+    M.part.block_ptr.swap(P.block_ptr);
+    M.part.h_block_ptr.swap(P.h_block_ptr);
+    M.part.nnz = P.nnz;
+    M.part.rb = P.rb;
+    M.part.cb = P.cb;
+    M.part.ibits = P.ibits;
+    M.part.ubits = P.ubits;
+    M.mu = mu;
+    M.loaded = true;
+    M.bf16_valid = false;
+}
+
+void run_epoch(bmf_ctx *c, const HP &hp) {
+    Model &M = c->M;
+    if (!M.loaded) BMF_FAIL(BMF_E_STATE, "no ratings loaded");
+    std::vector<int32_t> order(M.b);
+    schedule(M.b, M.order_seed, M.epoch, M.order_mode, order.data());
+    sgd_epoch(M, order.data(), hp);
+    M.epoch += 1;
+    M.bf16_valid = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+bmf_status bmf_create(int64_t m, int64_t n, int32_t k, int32_t b, bmf_ctx **out) {
+    if (!out) return BMF_E_INVAL;
+    *out = nullptr;
+    if (m < 1 || n < 1 || k < 1 || k > 1024 || b < 1 || m >= INT32_MAX || n >= INT32_MAX) {
+        g_create_error = "invalid sizes: need m, n in [1, 2^31), 1 <= k <= 1024, b >= 1";
+        return BMF_E_INVAL;
+    }
+    if ((int64_t)b * b > (int64_t)1 << 26) {
+        g_create_error = "block grid too large (b*b must be at most 2^26)";
+        return BMF_E_INVAL;
+    }
+    bmf_ctx *c = new (std::nothrow) bmf_ctx();
+    if (!c) {
+        g_create_error = "host allocation failed";
+        return BMF_E_NOMEM;
+    }
+    try {
+        Model &M = c->M;
+        BMF_HIP(hipGetDevice(&M.device));
+        BMF_HIP(hipStreamCreateWithFlags(&M.own_stream, hipStreamNonBlocking));
+        M.stream = M.own_stream;
+        M.m = m;
+        M.n = n;
+        M.k = k;
+        M.b = b;
+        M.P.alloc((size_t)m * k * 4);
+        M.Q.alloc((size_t)n * k * 4);
+        M.bu.alloc((size_t)m * 4);
+        M.bi.alloc((size_t)n * 4);
+        M.red.alloc(1 << 16);
+        init_model_factors(M);
+        BMF_HIP(hipStreamSynchronize(M.stream));
+    } catch (const Error &e) {
+        g_create_error = e.msg;
+        bmf_destroy(c);
+        return e.code == BMF_E_DEVICE ? BMF_E_DEVICE : e.code;
+    } catch (...) {
+        g_create_error = "unexpected internal exception";
+        bmf_destroy(c);
+        return BMF_E_DEVICE;
+    }
+    *out = c;
+    return BMF_OK;
+}
+
+void bmf_destroy(bmf_ctx *c) {
+    if (!c) return;
+    Model &M = c->M;
+    (void)hipSetDevice(M.device);
+    if (M.stream) (void)hipStreamSynchronize(M.stream);
+    for (auto &pr : M.pending) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
+    for (auto e : M.spare_events) (void)hipEventDestroy(e);
+    if (M.own_stream) (void)hipStreamDestroy(M.own_stream);
+    delete c;  // DevBuf destructors free device memory
+}
+
+const char *bmf_last_error(const bmf_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+bmf_status bmf_set_option(bmf_ctx *c, int32_t key, int64_t value) {
+    return guarded(c, false, [&] {
+        Model &M = c->M;
+        switch (key) {
+        case BMF_OPT_SEED:
+            M.seed = (uint64_t)value;
+            init_model_factors(M);
+            break;
+        case BMF_OPT_ORDER_SEED: M.order_seed = (uint64_t)value; break;
+        case BMF_OPT_STRATUM_ORDER:
+            if (value != 0 && value != 1) BMF_FAIL(BMF_E_INVAL, "stratum order must be 0 or 1");
+            M.order_mode = (int)value;
+            break;
+        case BMF_OPT_MU_MODE:
+            if (value != 0 && value != 1) BMF_FAIL(BMF_E_INVAL, "mu mode must be 0 or 1");
+            M.mu_mode = (int)value;
+            break;
+        case BMF_OPT_STREAM:
+            BMF_HIP(hipStreamSynchronize(M.stream));
+            M.stream = value ? reinterpret_cast<hipStream_t>(value) : M.own_stream;
+            break;
+        case BMF_OPT_SGD_KERNEL:
+            if (value < 0 || value > 2) BMF_FAIL(BMF_E_INVAL, "SGD kernel must be 0, 1 or 2");
+            M.sgd_kernel = (int)value;
+            break;
+        case BMF_OPT_PERSISTENT:
+            if (value != 0 && value != 1) BMF_FAIL(BMF_E_INVAL, "persistent must be 0 or 1");
+            M.persistent = (int)value;
+            break;
+        default: BMF_FAIL(BMF_E_INVAL, "unknown option " + std::to_string(key));
+        }
+    });
+}
+
+bmf_status bmf_synchronize(bmf_ctx *c) {
+    return guarded(c, false, [&] { BMF_HIP(hipStreamSynchronize(c->M.stream)); });
+}
+
+bmf_status bmf_load_ratings(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r, int64_t nnz) {
+    return guarded(c, false, [&] { load_common(c, u, i, r, nnz, false); });
+}
+
+bmf_status bmf_load_ratings_dev(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r, int64_t nnz) {
+    return guarded(c, false, [&] { load_common(c, u, i, r, nnz, true); });
+}
+
+bmf_status bmf_epoch(bmf_ctx *c, float lr, float reg) {
+    return guarded(c, false, [&] {
+        const float hp[8] = {lr, reg, lr, reg, lr, reg, lr, reg};
+        check_finite_hp(hp);
+        run_epoch(c, hp_uniform(lr, reg));
+    });
+}
+
+bmf_status bmf_epoch_hp(bmf_ctx *c, const float hp[8]) {
+    return guarded(c, false, [&] {
+        if (!hp) BMF_FAIL(BMF_E_INVAL, "null hyper-parameters");
+        check_finite_hp(hp);
+        run_epoch(c, hp_from(hp));
+    });
+}
+
+bmf_status bmf_epoch_count(const bmf_ctx *c, int32_t *out) {
+    if (!c || !out) return BMF_E_INVAL;
+    *out = c->M.epoch;
+    return BMF_OK;
+}
+
+bmf_status bmf_get_schedule(const bmf_ctx *c, int32_t epoch, int32_t *order) {
+    if (!c || !order || epoch < 0) return BMF_E_INVAL;
+    schedule(c->M.b, c->M.order_seed, epoch, c->M.order_mode, order);
+    return BMF_OK;
+}
+
+bmf_status bmf_stratum_order(int32_t b, uint64_t seed, int32_t epoch, int32_t mode, int32_t *order) {
+    if (b < 1 || !order || epoch < 0 || (mode != 0 && mode != 1)) return BMF_E_INVAL;
+    schedule(b, seed, epoch, mode, order);
+    return BMF_OK;
+}
+
+bmf_status bmf_get_partition(bmf_ctx *c, int64_t *block_ptr, int32_t *perm) {
+    return guarded(c, false, [&] {
+        Model &M = c->M;
+        if (!M.loaded) BMF_FAIL(BMF_E_STATE, "no ratings loaded");
+        if (block_ptr)
+            std::memcpy(block_ptr, M.part.h_block_ptr.data(), M.part.h_block_ptr.size() * sizeof(int64_t));
+        if (perm && M.part.nnz) {
+            BMF_HIP(hipMemcpyAsync(perm, M.part.perm.p, M.part.nnz * 4, hipMemcpyDeviceToHost, M.stream));
+            BMF_HIP(hipStreamSynchronize(M.stream));
+        }
+    });
+}
+
+bmf_status bmf_get_factors(bmf_ctx *c, float *P, float *Q, float *bu, float *bi, double *mu) {
+    return guarded(c, true, [&] {
+        Model &M = c->M;
+        BMF_HIP(hipStreamSynchronize(M.stream));
+        if (P) BMF_HIP(hipMemcpy(P, M.P.p, (size_t)M.m * M.k * 4, hipMemcpyDeviceToHost));
+        if (Q) BMF_HIP(hipMemcpy(Q, M.Q.p, (size_t)M.n * M.k * 4, hipMemcpyDeviceToHost));
+        if (bu) BMF_HIP(hipMemcpy(bu, M.bu.p, (size_t)M.m * 4, hipMemcpyDeviceToHost));
+        if (bi) BMF_HIP(hipMemcpy(bi, M.bi.p, (size_t)M.n * 4, hipMemcpyDeviceToHost));
+        if (mu) *mu = M.mu;
+    });
+}
+
+bmf_status bmf_set_factors(bmf_ctx *c, const float *P, const float *Q, const float *bu, const float *bi,
+                           const double *mu) {
+    return guarded(c, false, [&] {
+        Model &M = c->M;
+        if (mu && !std::isfinite(*mu)) BMF_FAIL(BMF_E_INVAL, "mu must be finite");
+        BMF_HIP(hipStreamSynchronize(M.stream));
+        if (P) BMF_HIP(hipMemcpy(M.P.p, P, (size_t)M.m * M.k * 4, hipMemcpyHostToDevice));
+        if (Q) BMF_HIP(hipMemcpy(M.Q.p, Q, (size_t)M.n * M.k * 4, hipMemcpyHostToDevice));
+        if (bu) BMF_HIP(hipMemcpy(M.bu.p, bu, (size_t)M.m * 4, hipMemcpyHostToDevice));
+        if (bi) BMF_HIP(hipMemcpy(M.bi.p, bi, (size_t)M.n * 4, hipMemcpyHostToDevice));
+        if (mu) M.mu = *mu;
+        M.bf16_valid = false;
+    });
+}
+
+bmf_status bmf_factor_ptrs(bmf_ctx *c, float **P, float **Q, float **bu, float **bi) {
+    return guarded(c, false, [&] {
+        if (P) *P = c->M.P.as<float>();
+        if (Q) *Q = c->M.Q.as<float>();
+        if (bu) *bu = c->M.bu.as<float>();
+        if (bi) *bi = c->M.bi.as<float>();
+        c->M.bf16_valid = false;  // the caller may write through these
+    });
+}
+
+bmf_status bmf_rmse(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r, int64_t cnt, double *out) {
+    return guarded(c, false, [&] {
+        Model &M = c->M;
+        if (!out) BMF_FAIL(BMF_E_INVAL, "null output");
+        double s = 0.0;
+        int64_t total = 0;
+        if (!u) {
+            if (!M.loaded) BMF_FAIL(BMF_E_STATE, "no ratings loaded");
+            total = M.part.nnz;
+            s = sq_residual_sum(M, M.cu.as<int32_t>(), M.ci.as<int32_t>(), M.cr.as<float>(), total, nullptr, M.red);
+        } else {
+            if (cnt < 0 || (cnt > 0 && (!i || !r))) BMF_FAIL(BMF_E_INVAL, "bad evaluation arrays");
+            for (int64_t t = 0; t < cnt; ++t)
+                if (u[t] < 0 || u[t] >= M.m || i[t] < 0 || i[t] >= M.n || !std::isfinite(r[t]))
+                    BMF_FAIL(BMF_E_RANGE, "evaluation rating " + std::to_string(t) + " out of range");
+            DevBuf du, di, dr;
+            upload(du, u, cnt, M.stream);
+            upload(di, i, cnt, M.stream);
+            upload(dr, r, cnt, M.stream);
+            total = cnt;
+            s = sq_residual_sum(M, du.as<int32_t>(), di.as<int32_t>(), dr.as<float>(), cnt, nullptr, M.red);
+        }
+        *out = total > 0 ? std::sqrt(s / (double)total) : 0.0;
+    });
+}
+
+bmf_status bmf_loss(bmf_ctx *c, const float hp[8], double *out) {
+    return guarded(c, false, [&] {
+        Model &M = c->M;
+        if (!out || !hp) BMF_FAIL(BMF_E_INVAL, "null argument");
+        if (!M.loaded) BMF_FAIL(BMF_E_STATE, "no ratings loaded");
+        const HP h = hp_from(hp);
+        *out = sq_residual_sum(M, M.cu.as<int32_t>(), M.ci.as<int32_t>(), M.cr.as<float>(), M.part.nnz, &h, M.red);
+    });
+}
+
+static void check_topk_args(const Model &M, int64_t nu, int32_t K, int32_t precision, int32_t Kc) {
+    if (nu < 0) BMF_FAIL(BMF_E_INVAL, "nu < 0");
+    if (K < 1 || K > 512) BMF_FAIL(BMF_E_INVAL, "K must be in [1, 512]");
+    if (precision != 0 && precision != 1) BMF_FAIL(BMF_E_INVAL, "precision must be 0 or 1");
+    if (precision == 1 && Kc != 0 && (Kc < K || Kc > 1008)) BMF_FAIL(BMF_E_INVAL, "Kc must be 0 or in [K, 1008]");
+    if (M.k > 256) BMF_FAIL(BMF_E_INVAL, "top-K scoring supports k <= 256");
+}
+
+static bmf_status topk_host(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t precision, int32_t Kc,
+                            int32_t *items_out, float *scores_out) {
+    return guarded(c, false, [&] {
+        Model &M = c->M;
+        check_topk_args(M, nu, K, precision, Kc);
+        if (nu > 0 && (!users || !items_out || !scores_out)) BMF_FAIL(BMF_E_INVAL, "null array");
+        for (int64_t q = 0; q < nu; ++q)
+            if (users[q] < 0 || users[q] >= M.m) BMF_FAIL(BMF_E_RANGE, "user id " + std::to_string(users[q]) + " out of range");
+        if (nu == 0) return;
+        DevBuf du, di, ds;
+        upload(du, users, nu, M.stream);
+        di.alloc((size_t)nu * K * 4);
+        ds.alloc((size_t)nu * K * 4);
+        topk_run(M, du.as<int32_t>(), nu, K, precision, Kc, di.as<int32_t>(), ds.as<float>());
+        BMF_HIP(hipMemcpyAsync(items_out, di.p, (size_t)nu * K * 4, hipMemcpyDeviceToHost, M.stream));
+        BMF_HIP(hipMemcpyAsync(scores_out, ds.p, (size_t)nu * K * 4, hipMemcpyDeviceToHost, M.stream));
+        BMF_HIP(hipStreamSynchronize(M.stream));
+    });
+}
+
+bmf_status bmf_topk(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t *items_out, float *scores_out) {
+    return topk_host(c, users, nu, K, 0, 0, items_out, scores_out);
+}
+
+bmf_status bmf_topk_bf16(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t Kc, int32_t *items_out,
+                         float *scores_out) {
+    return topk_host(c, users, nu, K, 1, Kc, items_out, scores_out);
+}
+
+bmf_status bmf_topk_dev(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t precision, int32_t Kc,
+                        int32_t *items_out, float *scores_out) {
+    return guarded(c, false, [&] {
+        check_topk_args(c->M, nu, K, precision, Kc);
+        if (nu > 0 && (!users || !items_out || !scores_out)) BMF_FAIL(BMF_E_INVAL, "null array");
+        topk_run(c->M, users, nu, K, precision, Kc, items_out, scores_out);
+    });
+}
+
+bmf_status bmf_foldin(bmf_ctx *c, const int32_t *items, const float *r, int32_t nr, int32_t passes, float lr,
+                      float reg, float *p_out, float *bu_out) {
+    return guarded(c, false, [&] {
+        Model &M = c->M;
+        if (nr < 0 || passes < 0 || !p_out || !bu_out || (nr > 0 && (!items || !r)))
+            BMF_FAIL(BMF_E_INVAL, "bad fold-in arguments");
+        if (!std::isfinite(lr) || !std::isfinite(reg)) BMF_FAIL(BMF_E_INVAL, "non-finite hyper-parameter");
+        for (int32_t t = 0; t < nr; ++t)
+            if (items[t] < 0 || items[t] >= M.n || !std::isfinite(r[t]))
+                BMF_FAIL(BMF_E_RANGE, "fold-in rating " + std::to_string(t) + " out of range");
+        DevBuf di, dr, dp, db;
+        upload(di, items, nr, M.stream);
+        upload(dr, r, nr, M.stream);
+        dp.alloc((size_t)M.k * 4);
+        db.alloc(4);
+        foldin_run(M, di.as<int32_t>(), dr.as<float>(), nr, passes, hp_uniform(lr, reg), dp.as<float>(),
+                   db.as<float>());
+        BMF_HIP(hipMemcpy(p_out, dp.p, (size_t)M.k * 4, hipMemcpyDeviceToHost));
+        BMF_HIP(hipMemcpy(bu_out, db.p, 4, hipMemcpyDeviceToHost));
+    });
+}
+
+bmf_status bmf_sgd_timing(bmf_ctx *c, double *ms, int64_t *launches, int32_t reset) {
+    return guarded(c, false, [&] {
+        Model &M = c->M;
+        harvest_timing(M, true);
+        if (ms) *ms = M.sgd_ms;
+        if (launches) *launches = M.sgd_launches;
+        if (reset) {
+            M.sgd_ms = 0.0;
+            M.sgd_launches = 0;
+        }
+    });
+}
+
+bmf_status bmf_debug_wave_sum(const float *in64, float *out192) {
+    if (!in64 || !out192) return BMF_E_INVAL;
+    try {
+        DevBuf di, dout;
+        di.alloc(64 * 4);
+        dout.alloc(192 * 4);
+        BMF_HIP(hipMemcpy(di.p, in64, 64 * 4, hipMemcpyHostToDevice));
+        debug_wave_sum(di.as<float>(), dout.as<float>(), nullptr);
+        BMF_HIP(hipMemcpy(out192, dout.p, 192 * 4, hipMemcpyDeviceToHost));
+    } catch (const Error &e) {
+        g_create_error = e.msg;
+        return e.code;
+    }
+    return BMF_OK;
+}
+
+}  // extern "C"

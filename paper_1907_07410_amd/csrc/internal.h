@@ -1,0 +1,153 @@
+// Internal declarations shared by the libbmf translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bmf.h"
+
+namespace bmf {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+    bmf_status code;
+    std::string msg;
+};
+
+#define BMF_HIP(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::bmf::Error{BMF_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define BMF_FAIL(code, msg) throw ::bmf::Error{(code), (msg)}
+
+// ---------------------------------------------------------- hyper-params
+// {alpha_p, beta_p, alpha_q, beta_q, alpha_bu, beta_bu, alpha_bi, beta_bi}
+struct HP {
+    float a_p, b_p, a_q, b_q, a_bu, b_bu, a_bi, b_bi;
+};
+
+// A rating inside a block: local row (u - br*rb) and column (i - bc*cb)
+// packed as (row << ibits) | col, and the value.
+struct Rec {
+    uint32_t ui;
+    float r;
+};
+
+// Device buffer owned by a context.
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void alloc(size_t n);
+    void free_();
+    template <class T> T *as() const { return static_cast<T *>(p); }
+    ~DevBuf() { free_(); }
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    void swap(DevBuf &o) {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+    }
+};
+
+// Partition of a rating set on the device.
+struct Partition {
+    int64_t nnz = 0;
+    int64_t rb = 1, cb = 1;
+    int ibits = 0, ubits = 0;
+    DevBuf recs;       // Rec[nnz], processing order
+    DevBuf perm;       // int32[nnz], position -> input index
+    DevBuf block_ptr;  // int64[b*b + 1]
+    std::vector<int64_t> h_block_ptr;
+};
+
+// --------------------------------------------------------------- context
+struct Model {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    int64_t m = 0, n = 0;
+    int k = 0, b = 0;
+    uint64_t seed = 1001, order_seed = 2001;
+    int order_mode = 0, mu_mode = 0, sgd_kernel = 0, persistent = 0;
+    DevBuf P, Q, bu, bi;
+    double mu = 0.0;
+    // training data
+    bool loaded = false;
+    DevBuf cu, ci, cr;  // training COO as given (int32, int32, f32)
+    Partition part;
+    int32_t epoch = 0;
+    // bf16 copies for scoring
+    DevBuf Pb, Qb;
+    bool bf16_valid = false;
+    // timing of SGD launches: event pairs still pending, and spare events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+    std::vector<hipEvent_t> spare_events;
+    double sgd_ms = 0.0;
+    int64_t sgd_launches = 0;
+    // scratch for reductions / top-K
+    DevBuf red;
+    DevBuf scratch;
+};
+
+}  // namespace bmf
+
+struct bmf_ctx {
+    bmf::Model M;
+    bool poisoned = false;
+    std::string err;
+};
+
+namespace bmf {
+
+// ---------------------------------------------------------------- random
+uint64_t splitmix64(uint64_t seed, uint64_t j);
+void schedule(int b, uint64_t seed, int epoch, int mode, int32_t *order);
+
+// --------------------------------------------------------------- kernels
+// all launchers enqueue on `s` and throw Error on launch failure
+void launch_init_factors(float *A, int64_t rows, int k, uint64_t seed, int tag, hipStream_t s);
+void launch_fill(float *A, int64_t n, float v, hipStream_t s);
+
+// Validate COO: returns first bad index or -1 (synchronises).
+int64_t validate_coo(const int32_t *u, const int32_t *i, const float *r, int64_t nnz, int64_t m,
+                     int64_t n, DevBuf &scratch, hipStream_t s);
+// FP64 sum of r[0..nnz) in a fixed order (synchronises).
+double sum_f32_as_f64(const float *r, int64_t nnz, DevBuf &scratch, hipStream_t s);
+// Build a partition (synchronises).
+void build_partition(Partition &out, const int32_t *u, const int32_t *i, const float *r, int64_t nnz,
+                     int64_t m, int64_t n, int b, hipStream_t s);
+
+// SGD: run one epoch of strata in `order`.
+void sgd_epoch(Model &M, const int32_t *order, const HP &hp);
+
+// Evaluation: sum of squared residuals (FP64) over COO, optionally with
+// the regularisation terms (loss). Synchronises.
+double sq_residual_sum(const Model &M, const int32_t *u, const int32_t *i, const float *r, int64_t cnt,
+                       const HP *loss_hp, DevBuf &scratch);
+
+// Top-K
+void topk_run(Model &M, const int32_t *d_users, int64_t nu, int K, int precision, int Kc,
+              int32_t *d_items, float *d_scores);
+void foldin_run(Model &M, const int32_t *d_items, const float *d_r, int nr, int passes, const HP &hp,
+                float *d_p, float *d_bu);
+void foldin_launch(Model &M, const int32_t *d_items, const float *d_r, const int64_t *d_off, int64_t nreq,
+                   int max_cnt, int passes, const HP &hp, float *d_p, int64_t p_stride, float *d_bu);
+void ensure_bf16_items(Model &M);
+
+// Timing: take an event (from the spare list or new), and fold completed
+// pending pairs into sgd_ms (all of them, waiting, when `wait`).
+hipEvent_t take_event(Model &M);
+void harvest_timing(Model &M, bool wait);
+
+// Diagnostics: the three wavefront sums of 64 values (xor butterfly, DPP
+// butterfly, 16-lane row sums) on the device.
+void debug_wave_sum(const float *d_in, float *d_out, hipStream_t s);
+
+}  // namespace bmf

@@ -236,11 +236,12 @@ bmf_status bmf_stratum_order(int32_t b, uint64_t seed, int32_t epoch, int32_t mo
 
 /* ---------------------------------------------------------- diagnostics */
 
-/* Reduction self-check on the current device: out[0:64], out[64:128] and
- * out[128:192] receive, per lane, the 64-lane sum of in[0:64] by the
- * shuffle butterfly and by the DPP butterfly (both must be identical), and
- * the 16-lane row sums by DPP.  Host arrays. */
-bmf_status bmf_debug_wave_sum(const float *in64, float *out192);
+/* Reduction self-check on the current device: out[0:64], out[64:128],
+ * out[128:192] and out[192:256] receive, per lane, the 64-lane sum of
+ * in[0:64] by the shuffle butterfly, by the DPP butterfly, the 16-lane row
+ * sums by DPP, and the 64-lane sum by DPP plus permlane swaps.  The three
+ * full sums must be bit-identical.  Host arrays. */
+bmf_status bmf_debug_wave_sum(const float *in64, float *out256);
 
 #ifdef __cplusplus
 }

@@ -244,8 +244,8 @@ def stratum_order(b: int, seed: int, epoch: int, mode: int) -> np.ndarray:
 
 def debug_wave_sum(x) -> np.ndarray:
     x = _c(x, np.float32)
-    out = np.zeros(192, dtype=np.float32)
+    out = np.zeros(256, dtype=np.float32)
     st = lib.bmf_debug_wave_sum(_ptr(x), _ptr(out))
     if st != 0:
         raise BmfError(st, lib.bmf_last_error(None).decode())
-    return out.reshape(3, 64)
+    return out.reshape(4, 64)

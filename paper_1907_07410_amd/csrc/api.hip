@@ -426,15 +426,15 @@ bmf_status bmf_sgd_timing(bmf_ctx *c, double *ms, int64_t *launches, int32_t res
     });
 }
 
-bmf_status bmf_debug_wave_sum(const float *in64, float *out192) {
-    if (!in64 || !out192) return BMF_E_INVAL;
+bmf_status bmf_debug_wave_sum(const float *in64, float *out256) {
+    if (!in64 || !out256) return BMF_E_INVAL;
     try {
         DevBuf di, dout;
         di.alloc(64 * 4);
-        dout.alloc(192 * 4);
+        dout.alloc(256 * 4);
         BMF_HIP(hipMemcpy(di.p, in64, 64 * 4, hipMemcpyHostToDevice));
         debug_wave_sum(di.as<float>(), dout.as<float>(), nullptr);
-        BMF_HIP(hipMemcpy(out192, dout.p, 192 * 4, hipMemcpyDeviceToHost));
+        BMF_HIP(hipMemcpy(out256, dout.p, 256 * 4, hipMemcpyDeviceToHost));
     } catch (const Error &e) {
         g_create_error = e.msg;
         return e.code;

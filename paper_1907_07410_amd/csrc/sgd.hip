@@ -9,7 +9,7 @@
 //
 // Inside a block one wavefront walks the ratings in (u, i, t) order; lane f
 // owns latent factors f, f + 64, ... .  Every variant below performs the
-// same floating-point operations in the same order (rating_update), so all
+// same floating-point operations in the same order (the helpers below), so all
 // variants produce identical bits.
 #pragma clang fp contract(off)
 
@@ -97,49 +97,55 @@ __global__ __launch_bounds__(64) void sgd_global_kernel(const Rec *__restrict__ 
 }
 
 // ---------------------------------------------------------------- v1
-// LDS-staged kernel.  Workgroup = 4 waves.
+// LDS-staged kernel.  Workgroup = 4 waves: wave 0 runs the dependent
+// update chain, waves 1-3 move data.
 //  * The block column's item slice Q[i0 : i0+cb] and bi slice live in LDS
 //    for the whole block (read once, written back once).
-//  * Ratings go in chunks of 64.  While wave 0 runs the SGD chain over
-//    chunk c, waves 1-3 stage chunk c+1: its 64 records and, for every
-//    record that starts a new user run, that user's P row and bu into a
-//    double buffer.  One barrier per chunk.
-//  * Wave 0 keeps the current user's p and bu in registers for the whole
-//    run (a user's ratings are contiguous in (u, i) order) and writes them
-//    to global memory when the run ends.  A run that crosses a chunk
-//    boundary keeps its registers (the staged copy is stale then).
-//  * The next rating's item row and bias are read from LDS one rating ahead;
-//    when the next rating hits the same item (a duplicate pair) the freshly
-//    updated registers are forwarded instead.
+//  * Ratings go in chunks of 64.  While wave 0 works on chunk c, the helper
+//    waves (a) write back to global memory the user rows whose run ended in
+//    chunk c-1 and (b) stage chunk c+1: its records and, for every record
+//    that starts a user run, that user's P row and bu, into the other half
+//    of a double buffer.  One barrier per chunk.
+//  * Wave 0 touches no global memory: it keeps the current user's p and bu
+//    in registers (a user's ratings are contiguous in (u, i) order), reads
+//    the next rating's item row, item bias and (possibly new) user row from
+//    LDS one rating ahead, and after every rating writes the updated item
+//    row and bias back to the slice and the updated user row and bias to
+//    the rating's staging slot, where the helpers find the final values of
+//    each run.  The loop body has no branches: run switches and the
+//    forwarding of a just-updated item row (two consecutive ratings of the
+//    same item, i.e. a duplicate pair) are selects, and single-lane stores
+//    go through per-lane dummy addresses.
 constexpr int LDS_WG = 256;
 constexpr int CHUNK = 64;
+constexpr int NH = LDS_WG / WAVE - 1;       // helper waves
+constexpr int PER = (CHUNK + NH - 1) / NH;  // records per helper wave
 
 struct LdsLayout {
-    int k, ncols;
-    size_t q_off, bi_off, rec_off, p_off, bu_off, total;
+    size_t q_off, bi_off, rec_off, p_off, bu_off, dummy_off, total;
 };
 
 __host__ __device__ inline LdsLayout lds_layout(int k, int64_t cb) {
     LdsLayout L;
-    L.k = k;
-    L.ncols = (int)cb;
     size_t o = 0;
     L.q_off = o;
     o += (size_t)cb * k * 4;
     L.bi_off = o;
-    o += (size_t)cb * 4;
+    o += (size_t)cb * 4 + 64 * 4 * 4;  // slack: full-width reads of the last row stay inside
     o = (o + 15) & ~size_t(15);
     L.rec_off = o;
-    o += 2 * CHUNK * sizeof(Rec);
+    o += 3 * CHUNK * sizeof(Rec);  // records: triple buffer (wave 0 reads c, helpers read c-1, write c+1)
     L.p_off = o;
-    o += (size_t)2 * CHUNK * k * 4;
+    o += (size_t)2 * CHUNK * k * 4 + 64 * 4 * 4;
     L.bu_off = o;
     o += 2 * CHUNK * 4;
+    L.dummy_off = o;
+    o += 64 * 16 * 4;
     L.total = o;
     return L;
 }
 
-template <int KPL>
+template <int KPL, bool FULL>
 __global__ __launch_bounds__(LDS_WG) void sgd_lds_kernel(const Rec *__restrict__ recs,
                                                          const int64_t *__restrict__ block_ptr, int b, int s,
                                                          int64_t n, int64_t rb, int64_t cb, int ibits, int k,
@@ -152,6 +158,7 @@ __global__ __launch_bounds__(LDS_WG) void sgd_lds_kernel(const Rec *__restrict__
     Rec *rbuf = reinterpret_cast<Rec *>(smem + L.rec_off);
     float *Ps = reinterpret_cast<float *>(smem + L.p_off);
     float *bus = reinterpret_cast<float *>(smem + L.bu_off);
+    float *dummy = reinterpret_cast<float *>(smem + L.dummy_off);
 
     const int j = blockIdx.x;
     const int br = (j + s) % b;
@@ -170,116 +177,191 @@ __global__ __launch_bounds__(LDS_WG) void sgd_lds_kernel(const Rec *__restrict__
     for (int64_t x = tid; x < (int64_t)ncols * k; x += LDS_WG) Qs[x] = Q[i0 * k + x];
     for (int x = tid; x < ncols; x += LDS_WG) bis[x] = bi[i0 + x];
 
-    // helpers (waves 1..3): stage chunk c into buffer c & 1
+    // Helper wave hw owns records l = hw + NH*jj of every chunk (the same
+    // slots for write-back and staging, so its LDS reads of a slot precede
+    // its writes in program order).
+    const int hw = wave - 1;
+    const int lj = hw + NH * lane;  // this lane's record slot
+
+    // write back the user rows whose run ended in chunk c (buffer c & 1);
+    // `next_ul` is the local user of the record after the chunk (or ~0)
+    auto write_back = [&](int c, uint32_t next_ul) {
+        const int buf = c & 1;
+        const Rec *rb3 = rbuf + (c % 3) * CHUNK;
+        const int64_t cbeg = beg + (int64_t)c * CHUNK;
+        const int len = (int)std::min<int64_t>(CHUNK, end - cbeg);
+        const bool valid = lane < PER && lj < len;
+        uint32_t ul = 0, ul_next = next_ul;
+        if (valid) {
+            ul = rb3[lj].ui >> ibits;
+            if (lj + 1 < len) ul_next = rb3[lj + 1].ui >> ibits;
+        }
+        const bool run_end = valid && ul_next != ul;
+        if (run_end) bu[u0 + ul] = bus[buf * CHUNK + lj];
+        const uint64_t emask = __ballot(run_end);
+#pragma unroll
+        for (int jj = 0; jj < PER; ++jj) {
+            if ((emask >> jj) & 1ull) {
+                const int l = hw + NH * jj;
+                const int64_t urow = u0 + (int64_t)__builtin_amdgcn_readlane(ul, jj);
+#pragma unroll
+                for (int cc = 0; cc < KPL; ++cc) {
+                    const int f = lane + WAVE * cc;
+                    if (FULL || f < k) P[urow * k + f] = Ps[((size_t)buf * CHUNK + l) * k + f];
+                }
+            }
+        }
+    };
+
+    // stage chunk c into buffer c & 1: every P row a run starts with is
+    // loaded into registers before any is written, so the loads overlap
     auto stage = [&](int c) {
         const int buf = c & 1;
         const int64_t cbeg = beg + (int64_t)c * CHUNK;
         const int len = (int)std::min<int64_t>(CHUNK, end - cbeg);
-        for (int l = wave - 1; l < len; l += LDS_WG / WAVE - 1) {
-            const Rec rec = recs[cbeg + l];
-            const uint32_t ul = rec.ui >> ibits;
-            const bool start = (l == 0) || (recs[cbeg + l - 1].ui >> ibits) != ul;
-            if (lane == 0) {
-                rbuf[buf * CHUNK + l] = rec;
-                bus[buf * CHUNK + l] = bu[u0 + ul];
+        const bool valid = lane < PER && lj < len;
+        uint32_t ui = 0, uprev = 0xffffffffu;
+        float rr = 0.f;
+        if (valid) {
+            const Rec rc = recs[cbeg + lj];
+            ui = rc.ui;
+            rr = rc.r;
+            if (lj > 0) uprev = recs[cbeg + lj - 1].ui >> ibits;
+        }
+        const uint32_t ul = ui >> ibits;
+        const bool start = valid && (lj == 0 || uprev != ul);
+        const float buv = start ? bu[u0 + ul] : 0.f;
+        const uint64_t smask = __ballot(start);
+        float v[PER][KPL];
+#pragma unroll
+        for (int jj = 0; jj < PER; ++jj) {
+            if ((smask >> jj) & 1ull) {
+                const int64_t urow = u0 + (int64_t)__builtin_amdgcn_readlane(ul, jj);
+#pragma unroll
+                for (int cc = 0; cc < KPL; ++cc) {
+                    const int f = lane + WAVE * cc;
+                    v[jj][cc] = (FULL || f < k) ? P[urow * k + f] : 0.f;
+                }
             }
-            if (start)
-                for (int f = lane; f < k; f += WAVE) Ps[((size_t)buf * CHUNK + l) * k + f] = P[(u0 + ul) * k + f];
+        }
+        if (valid) {
+            rbuf[(c % 3) * CHUNK + lj] = Rec{ui, rr - mu};  // the rating minus mu, as every kernel forms it first
+            if (start) bus[buf * CHUNK + lj] = buv;
+        }
+#pragma unroll
+        for (int jj = 0; jj < PER; ++jj) {
+            if ((smask >> jj) & 1ull) {
+                const int l = hw + NH * jj;
+#pragma unroll
+                for (int cc = 0; cc < KPL; ++cc) {
+                    const int f = lane + WAVE * cc;
+                    if (FULL || f < k) Ps[((size_t)buf * CHUNK + l) * k + f] = v[jj][cc];
+                }
+            }
         }
     };
     if (wave > 0) stage(0);
     __syncthreads();
 
-    float p[KPL], q[KPL], qn[KPL];
-    float bu_cur = 0.f;
-    int64_t cur_u = -1;  // global id of the user whose p/bu sit in registers
+    // wave 0 state carried across chunks
+    float p[KPL], q_upd[KPL];
+#pragma unroll
+    for (int cc = 0; cc < KPL; ++cc) p[cc] = q_upd[cc] = 0.f;
+    float bu_cur = 0.f, bi_upd = 0.f;
+    uint32_t cur_ul = 0xffffffffu;
 
     for (int c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
         if (wave > 0) {
+            if (c > 0) {
+                const uint32_t nxt = rbuf[(c % 3) * CHUNK].ui >> ibits;  // first record of chunk c
+                write_back(c - 1, nxt);
+            }
             if (c + 1 < nchunks) stage(c + 1);
         } else {
-            const int buf = c & 1;
             const int64_t cbeg = beg + (int64_t)c * CHUNK;
-            const int len = (int)std::min<int64_t>(CHUNK, end - cbeg);
-            // lane l holds record l of the chunk
-            Rec myrec = rbuf[buf * CHUNK + (lane < len ? lane : 0)];
-            uint32_t rec_ui = myrec.ui;
-            float rec_r = myrec.r;
-            // prefetch the first rating's item row
+            const int len = __builtin_amdgcn_readfirstlane((int)std::min<int64_t>(CHUNK, end - cbeg));
+            const Rec myrec = rbuf[(c % 3) * CHUNK + lane];  // slots past len hold stale records, never used
+            const uint32_t rec_ui = myrec.ui;
+            const float rec_r = myrec.r;
+            float *Pbuf = Ps + (size_t)buf * CHUNK * k;
+            float *Bbuf = bus + buf * CHUNK;
+
+            // rating 0 of the chunk: item row and bias (the slice already
+            // holds every earlier update), staged user row
             uint32_t ui_n = __builtin_amdgcn_readlane(rec_ui, 0);
-            uint32_t il_n = ui_n & imask;
+            float r_n = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rec_r), 0));
+            float qn[KPL], pn[KPL];
 #pragma unroll
             for (int cc = 0; cc < KPL; ++cc) {
                 const int f = lane + WAVE * cc;
-                qn[cc] = f < k ? Qs[il_n * k + f] : 0.f;
+                const float a = Qs[(ui_n & imask) * k + f];
+                const float bb = Pbuf[f];
+                qn[cc] = (FULL || f < k) ? a : 0.f;
+                pn[cc] = (FULL || f < k) ? bb : 0.f;
             }
-            float bin = bis[il_n];
+            float bin = bis[ui_n & imask];
+            float bun = Bbuf[0];
+            bool same_item = false;
+            bool new_user = (ui_n >> ibits) != cur_ul;
+
             for (int l = 0; l < len; ++l) {
                 const uint32_t ui = ui_n;
-                const uint32_t il = il_n;
-                const float r = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rec_r), l));
-                const int64_t u = u0 + (ui >> ibits);
+                const uint32_t il = ui & imask;
+                const float r = r_n;
+                float q[KPL];
 #pragma unroll
-                for (int cc = 0; cc < KPL; ++cc) q[cc] = qn[cc];
-                const float bi0 = bin;
-                if (u != cur_u) {
-                    if (cur_u >= 0) {
-#pragma unroll
-                        for (int cc = 0; cc < KPL; ++cc) {
-                            const int f = lane + WAVE * cc;
-                            if (f < k) P[cur_u * k + f] = p[cc];
-                        }
-                        if (lane == 0) bu[cur_u] = bu_cur;
-                    }
-#pragma unroll
-                    for (int cc = 0; cc < KPL; ++cc) {
-                        const int f = lane + WAVE * cc;
-                        p[cc] = f < k ? Ps[((size_t)buf * CHUNK + l) * k + f] : 0.f;
-                    }
-                    bu_cur = bus[buf * CHUNK + l];
-                    cur_u = u;
+                for (int cc = 0; cc < KPL; ++cc) {
+                    q[cc] = same_item ? q_upd[cc] : qn[cc];
+                    p[cc] = new_user ? pn[cc] : p[cc];
                 }
-                // prefetch the next rating's item row (forwarded below when
-                // it is the same item)
-                const bool has_next = l + 1 < len;
-                if (has_next) {
-                    ui_n = __builtin_amdgcn_readlane(rec_ui, l + 1);
-                    il_n = ui_n & imask;
-#pragma unroll
-                    for (int cc = 0; cc < KPL; ++cc) {
-                        const int f = lane + WAVE * cc;
-                        qn[cc] = f < k ? Qs[il_n * k + f] : 0.f;
-                    }
-                    bin = bis[il_n];
-                }
-                const float dot = wave_sum_dpp(lane_dot(p, q));
-                const float e = residual(r, mu, bu_cur, bi0, dot);
-                factor_update(p, q, e, hp);
-                const float bi1 = bias_update(bi0, e, hp.a_bi, hp.b_bi);
-                bu_cur = bias_update(bu_cur, e, hp.a_bu, hp.b_bu);
+                const float bi0 = same_item ? bi_upd : bin;
+                const float bu0 = new_user ? bun : bu_cur;
+                // one rating ahead
+                const int ln = (l + 1 < len) ? l + 1 : l;
+                ui_n = __builtin_amdgcn_readlane(rec_ui, ln);
+                r_n = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rec_r), ln));
 #pragma unroll
                 for (int cc = 0; cc < KPL; ++cc) {
                     const int f = lane + WAVE * cc;
-                    if (f < k) Qs[il * k + f] = q[cc];
+                    const float a = Qs[(ui_n & imask) * k + f];
+                    const float bb = Pbuf[(size_t)ln * k + f];
+                    qn[cc] = (FULL || f < k) ? a : 0.f;
+                    pn[cc] = (FULL || f < k) ? bb : 0.f;
                 }
-                if (lane == 0) bis[il] = bi1;
-                if (has_next && il_n == il) {
+                bin = bis[ui_n & imask];
+                bun = Bbuf[ln];
+                same_item = (ui_n & imask) == il;
+                new_user = (ui_n >> ibits) != (ui >> ibits);
+                // the update (same operations as the reference kernel)
+                const float cres = (r - bu0) - bi0;  // r already holds rating - mu
+                const float dot = wave_sum_perm(lane_dot(p, q));
+                const float e = cres - dot;
+                factor_update(p, q, e, hp);
+                bi_upd = bias_update(bi0, e, hp.a_bi, hp.b_bi);
+                bu_cur = bias_update(bu0, e, hp.a_bu, hp.b_bu);
 #pragma unroll
-                    for (int cc = 0; cc < KPL; ++cc) qn[cc] = q[cc];
-                    bin = bi1;
+                for (int cc = 0; cc < KPL; ++cc) {
+                    const int f = lane + WAVE * cc;
+                    q_upd[cc] = q[cc];
+                    float *qa = (FULL || f < k) ? &Qs[il * k + f] : &dummy[lane];
+                    float *pa = (FULL || f < k) ? &Pbuf[(size_t)l * k + f] : &dummy[lane];
+                    *qa = q[cc];
+                    *pa = p[cc];
+                }
+                {
+                    float *ba = lane == 0 ? &bis[il] : &dummy[lane];
+                    float *ua = lane == 0 ? &Bbuf[l] : &dummy[64 + lane];
+                    *ba = bi_upd;
+                    *ua = bu_cur;
                 }
             }
+            cur_ul = __builtin_amdgcn_readlane(rec_ui, len - 1) >> ibits;
         }
         __syncthreads();
     }
-    if (wave == 0 && cur_u >= 0) {
-#pragma unroll
-        for (int cc = 0; cc < KPL; ++cc) {
-            const int f = lane + WAVE * cc;
-            if (f < k) P[cur_u * k + f] = p[cc];
-        }
-        if (lane == 0) bu[cur_u] = bu_cur;
-    }
+    // the last chunk's runs all end here
+    if (wave > 0) write_back(nchunks - 1, 0xffffffffu);
     __syncthreads();
     for (int64_t x = tid; x < (int64_t)ncols * k; x += LDS_WG) Q[i0 * k + x] = Qs[x];
     for (int x = tid; x < ncols; x += LDS_WG) bi[i0 + x] = bis[x];
@@ -287,30 +369,27 @@ __global__ __launch_bounds__(LDS_WG) void sgd_lds_kernel(const Rec *__restrict__
 
 // ---------------------------------------------------------------- host
 template <int KPL>
-static void launch_stratum(Model &M, int s, const HP &hp, int variant, size_t lds_bytes) {
+static void launch_global(Model &M, int s, const HP &hp) {
     const Partition &Pt = M.part;
-    const float mu = (float)M.mu;
-    if (variant == 2) {
-        sgd_lds_kernel<KPL><<<M.b, LDS_WG, lds_bytes, M.stream>>>(
-            Pt.recs.as<Rec>(), Pt.block_ptr.as<int64_t>(), M.b, s, M.n, Pt.rb, Pt.cb, Pt.ibits, M.k, M.P.as<float>(),
-            M.Q.as<float>(), M.bu.as<float>(), M.bi.as<float>(), mu, hp);
-    } else {
-        sgd_global_kernel<KPL><<<M.b, 64, 0, M.stream>>>(Pt.recs.as<Rec>(), Pt.block_ptr.as<int64_t>(), M.b, s,
-                                                          Pt.rb, Pt.cb, Pt.ibits, M.k, M.P.as<float>(),
-                                                          M.Q.as<float>(), M.bu.as<float>(), M.bi.as<float>(), mu,
-                                                          hp);
-    }
+    sgd_global_kernel<KPL><<<M.b, 64, 0, M.stream>>>(Pt.recs.as<Rec>(), Pt.block_ptr.as<int64_t>(), M.b, s, Pt.rb,
+                                                      Pt.cb, Pt.ibits, M.k, M.P.as<float>(), M.Q.as<float>(),
+                                                      M.bu.as<float>(), M.bi.as<float>(), (float)M.mu, hp);
     BMF_HIP(hipGetLastError());
 }
 
-template <int KPL>
-static void set_lds_attr(size_t bytes) {
-    static size_t done = 0;
-    if (bytes > done) {
-        BMF_HIP(hipFuncSetAttribute((const void *)sgd_lds_kernel<KPL>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)bytes));
-        done = bytes;
+template <int KPL, bool FULL>
+static void launch_lds(Model &M, int s, const HP &hp, size_t lds_bytes) {
+    static size_t attr_done = 0;  // per instantiation
+    if (lds_bytes > attr_done) {
+        BMF_HIP(hipFuncSetAttribute((const void *)sgd_lds_kernel<KPL, FULL>,
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+        attr_done = lds_bytes;
     }
+    const Partition &Pt = M.part;
+    sgd_lds_kernel<KPL, FULL><<<M.b, LDS_WG, lds_bytes, M.stream>>>(
+        Pt.recs.as<Rec>(), Pt.block_ptr.as<int64_t>(), M.b, s, M.n, Pt.rb, Pt.cb, Pt.ibits, M.k, M.P.as<float>(),
+        M.Q.as<float>(), M.bu.as<float>(), M.bi.as<float>(), (float)M.mu, hp);
+    BMF_HIP(hipGetLastError());
 }
 
 static int max_lds_bytes(int device) {
@@ -322,38 +401,46 @@ static int max_lds_bytes(int device) {
     return v;
 }
 
-void sgd_epoch(Model &M, const int32_t *order, const HP &hp) {
+static void launch_one(Model &M, int s, const HP &hp, int variant, size_t lds) {
     const int kpl = (M.k + WAVE - 1) / WAVE;
-    const LdsLayout L = lds_layout(M.k, M.part.cb);
-    int variant = M.sgd_kernel;
-    if (variant == 0) variant = ((int64_t)L.total <= max_lds_bytes(M.device)) ? 2 : 1;
-    if (variant == 2 && (int64_t)L.total > max_lds_bytes(M.device))
-        BMF_FAIL(BMF_E_STATE, "item slice does not fit in LDS for this block grid; use SGD kernel 1 or a larger b");
+    const bool full = M.k == WAVE * kpl;
     if (variant == 2) {
-        switch (kpl) {
-        case 1: set_lds_attr<1>(L.total); break;
-        case 2: set_lds_attr<2>(L.total); break;
-        case 3: set_lds_attr<3>(L.total); break;
-        case 4: set_lds_attr<4>(L.total); break;
+        switch (kpl * 2 + (full ? 1 : 0)) {
+        case 2: launch_lds<1, false>(M, s, hp, lds); return;
+        case 3: launch_lds<1, true>(M, s, hp, lds); return;
+        case 4: launch_lds<2, false>(M, s, hp, lds); return;
+        case 5: launch_lds<2, true>(M, s, hp, lds); return;
+        case 6: launch_lds<3, false>(M, s, hp, lds); return;
+        case 7: launch_lds<3, true>(M, s, hp, lds); return;
+        case 8: launch_lds<4, false>(M, s, hp, lds); return;
+        case 9: launch_lds<4, true>(M, s, hp, lds); return;
         default: break;
         }
     }
+    switch (kpl) {
+    case 1: launch_global<1>(M, s, hp); break;
+    case 2: launch_global<2>(M, s, hp); break;
+    case 3: launch_global<3>(M, s, hp); break;
+    case 4: launch_global<4>(M, s, hp); break;
+    case 5: launch_global<5>(M, s, hp); break;
+    case 6: launch_global<6>(M, s, hp); break;
+    case 7: launch_global<7>(M, s, hp); break;
+    case 8: launch_global<8>(M, s, hp); break;
+    default: launch_global<16>(M, s, hp); break;
+    }
+}
+
+void sgd_epoch(Model &M, const int32_t *order, const HP &hp) {
+    const int kpl = (M.k + WAVE - 1) / WAVE;
+    const LdsLayout L = lds_layout(M.k, M.part.cb);
+    const bool fits = kpl <= 4 && (int64_t)L.total <= max_lds_bytes(M.device);
+    int variant = M.sgd_kernel;
+    if (variant == 0) variant = fits ? 2 : 1;
+    if (variant == 2 && !fits)
+        BMF_FAIL(BMF_E_STATE, "item slice does not fit in LDS for this block grid; use SGD kernel 1 or a larger b");
     hipEvent_t ev0 = take_event(M), ev1 = take_event(M);
     BMF_HIP(hipEventRecord(ev0, M.stream));
-    for (int pos = 0; pos < M.b; ++pos) {
-        const int s = order[pos];
-        switch (kpl) {
-        case 1: launch_stratum<1>(M, s, hp, variant, L.total); break;
-        case 2: launch_stratum<2>(M, s, hp, variant, L.total); break;
-        case 3: launch_stratum<3>(M, s, hp, variant, L.total); break;
-        case 4: launch_stratum<4>(M, s, hp, variant, L.total); break;
-        case 5: launch_stratum<5>(M, s, hp, 1, 0); break;
-        case 6: launch_stratum<6>(M, s, hp, 1, 0); break;
-        case 7: launch_stratum<7>(M, s, hp, 1, 0); break;
-        case 8: launch_stratum<8>(M, s, hp, 1, 0); break;
-        default: launch_stratum<16>(M, s, hp, 1, 0); break;
-        }
-    }
+    for (int pos = 0; pos < M.b; ++pos) launch_one(M, order[pos], hp, variant, L.total);
     BMF_HIP(hipEventRecord(ev1, M.stream));
     M.pending.emplace_back(ev0, ev1);
     M.sgd_launches += M.b;
@@ -397,9 +484,11 @@ __global__ void debug_wave_sum_kernel(const float *in, float *out) {
     const float a = wave_sum_xor(v);
     const float b = wave_sum_dpp(v);
     const float c = row16_sum(v);
+    const float d = wave_sum_perm(v);
     out[lane] = a;
     out[64 + lane] = b;
     out[128 + lane] = c;
+    out[192 + lane] = d;
 }
 
 void debug_wave_sum(const float *d_in, float *d_out, hipStream_t s) {

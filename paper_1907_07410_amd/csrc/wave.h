@@ -65,6 +65,25 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
     return v;
 }
 
+// Full 64-lane sum: row16_sum, then rows (0,1), (2,3) and halves combined
+// with the gfx950 permlane swaps.  permlane16_swap(v, v) returns
+// {rows 0,0,2,2 ; rows 1,1,3,3} of v, permlane32_swap(v, v) returns
+// {halves lo,lo ; hi,hi}: adding the two results gives every lane the
+// partner sums of the xor butterfly's last two levels, with the same
+// association order (so the bits equal wave_sum_xor's).
+__device__ __forceinline__ float wave_sum_perm(float v) {
+    v = row16_sum(v);
+    {
+        const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+        v = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+    }
+    {
+        const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+        v = __uint_as_float(s[0]) + __uint_as_float(s[1]);
+    }
+    return v;
+}
+
 __device__ __forceinline__ uint32_t float_to_ordered(float f) {
     uint32_t b = __float_as_uint(f);
     return (b & 0x80000000u) ? ~b : (b | 0x80000000u);

@@ -44,6 +44,7 @@ def test_wave_reductions_agree_bitwise(B):
         x = (rng.standard_normal(64) * 10 ** rng.uniform(-3, 3, 64)).astype(np.float32)
         out = B.debug_wave_sum(x)
         assert np.array_equal(out[0].view(np.uint32), out[1].view(np.uint32)), trial
+        assert np.array_equal(out[0].view(np.uint32), out[3].view(np.uint32)), trial
         assert np.all(out[0] == out[0][0])
         assert abs(float(out[0][0]) - float(x.astype(np.float64).sum())) <= 1e-5 * np.abs(x).sum()
         rows = x.reshape(4, 16).astype(np.float64).sum(axis=1)

@@ -76,11 +76,10 @@ typedef enum {
      * 2 = LDS-staged item slice kernel.  All produce the same update
      * sequence; the value only changes speed. */
     BMF_OPT_SGD_KERNEL = 5,
-    /* stratum synchronisation: 0 = one launch per stratum (default),
-     * 1 = one persistent launch per epoch with per-row and per-column
-     * progress counters (falls back to 0 when the grid cannot be
-     * co-resident). */
-    BMF_OPT_PERSISTENT = 6
+    /* waves per workgroup of the LDS-staged SGD kernel: 4 or 8 (one wave
+     * runs the update chain, the others stage data); default 4.  On a
+     * batch, 0 lets the autotuner choose.  Does not change results. */
+    BMF_OPT_WAVES_PER_BLOCK = 6
 } bmf_option;
 
 /* ------------------------------------------------------------- lifetime */
@@ -233,6 +232,47 @@ bmf_status bmf_sgd_timing(bmf_ctx *c, double *ms, int64_t *launches, int32_t res
  * same rule as BMF_OPT_STRATUM_ORDER (mode 0 identity, mode 1 seeded
  * Fisher-Yates).  Host-only; order[b].  Errors: BMF_E_INVAL. */
 bmf_status bmf_stratum_order(int32_t b, uint64_t seed, int32_t epoch, int32_t mode, int32_t *order);
+
+/* -------------------------------------------------------------- batched */
+
+/* Many independent problems of uneven size trained together.  Each launch
+ * runs one global stratum position (epoch * b_p + position in the epoch's
+ * order) of every problem that has one, i.e. the blocks of up to nprob
+ * strata at once (Section 3's rule that blocks sharing no row or column are
+ * independent, applied within and across problems); successive positions
+ * follow in stream order.  Per problem the results are bit-identical to
+ * training that problem alone with the same grid and options.
+ * m[nprob], n[nprob]: sizes; k (1..128) shared; b[nprob]: block grid per
+ * problem, or b == NULL / b[p] == 0 for the autotuner (cost model of the
+ * per-epoch dependency chain and block staging, fitted by timed epochs of
+ * the largest problem; it also picks the waves per workgroup).
+ * Errors: BMF_E_INVAL, BMF_E_NOMEM, BMF_E_DEVICE. */
+bmf_status bmf_batch_create(int32_t nprob, const int64_t *m, const int64_t *n, int32_t k, const int32_t *b,
+                            bmf_batch **out);
+void bmf_batch_destroy(bmf_batch *B);
+const char *bmf_batch_last_error(const bmf_batch *B);
+/* BMF_OPT_SEED, BMF_OPT_ORDER_SEED, BMF_OPT_STRATUM_ORDER (applied to every
+ * problem) and BMF_OPT_WAVES_PER_BLOCK (0 = tuned); before any load. */
+bmf_status bmf_batch_set_option(bmf_batch *B, int32_t key, int64_t value);
+/* Ratings of problem p (host COO, as bmf_load_ratings); copied and
+ * validated now, partitioned when the grids are chosen. */
+bmf_status bmf_batch_load(bmf_batch *B, int32_t p, const int32_t *u, const int32_t *i, const float *r,
+                          int64_t nnz);
+/* Choose grids for every loaded problem and partition them (done
+ * implicitly by the first bmf_batch_epochs). */
+bmf_status bmf_batch_tune(bmf_batch *B);
+/* `epochs` epochs of every problem (max_p epochs * b_p launches); hp as in
+ * bmf_epoch_hp.  Waits for completion.  Every problem must be loaded. */
+bmf_status bmf_batch_epochs(bmf_batch *B, int32_t epochs, const float hp[8]);
+/* Borrowed context of problem p (valid until bmf_batch_destroy): use it
+ * for bmf_rmse, bmf_get_factors, bmf_topk, ...; do not destroy it. */
+bmf_status bmf_batch_problem(bmf_batch *B, int32_t p, bmf_ctx **out);
+/* Chosen grid and waves for problem p, and the model's epoch time (ms, -1
+ * when the grid was given). */
+bmf_status bmf_batch_info(bmf_batch *B, int32_t p, int32_t *b_out, int32_t *waves_out, double *predicted_ms);
+/* Time in batched epochs calls (HIP events on the batch stream around all
+ * their launches, ms) and the number of launches. */
+bmf_status bmf_batch_timing(bmf_batch *B, double *ms, int64_t *launches, int32_t reset);
 
 /* ---------------------------------------------------------- diagnostics */
 

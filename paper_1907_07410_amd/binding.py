@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbmf.so")
 
 BMF_OK, BMF_E_INVAL, BMF_E_RANGE, BMF_E_STATE, BMF_E_NOMEM, BMF_E_DEVICE = 0, -1, -2, -3, -4, -5
-OPT_SEED, OPT_ORDER_SEED, OPT_STRATUM_ORDER, OPT_MU_MODE, OPT_STREAM, OPT_SGD_KERNEL, OPT_PERSISTENT = range(7)
+OPT_SEED, OPT_ORDER_SEED, OPT_STRATUM_ORDER, OPT_MU_MODE, OPT_STREAM, OPT_SGD_KERNEL, OPT_WAVES_PER_BLOCK = range(7)
 
 _STATUS = {0: "BMF_OK", -1: "BMF_E_INVAL", -2: "BMF_E_RANGE", -3: "BMF_E_STATE", -4: "BMF_E_NOMEM",
            -5: "BMF_E_DEVICE"}
@@ -60,6 +60,16 @@ def _load():
         "bmf_sgd_timing": ([p, p, p, i32], i32),
         "bmf_debug_wave_sum": ([p, p], i32),
         "bmf_stratum_order": ([i32, C.c_uint64, i32, i32, p], i32),
+        "bmf_batch_create": ([i32, p, p, i32, p, pp], i32),
+        "bmf_batch_destroy": ([p], None),
+        "bmf_batch_last_error": ([p], C.c_char_p),
+        "bmf_batch_set_option": ([p, i32, i64], i32),
+        "bmf_batch_load": ([p, i32, p, p, p, i64], i32),
+        "bmf_batch_tune": ([p], i32),
+        "bmf_batch_epochs": ([p, i32, p], i32),
+        "bmf_batch_problem": ([p, i32, pp], i32),
+        "bmf_batch_info": ([p, i32, p, p, p], i32),
+        "bmf_batch_timing": ([p, p, p, i32], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -88,12 +98,20 @@ class Model:
 
     def __init__(self, m: int, n: int, k: int, b: int, seed: Optional[int] = None,
                  order_mode: Optional[int] = None, order_seed: Optional[int] = None,
-                 mu_mode: Optional[int] = None, sgd_kernel: Optional[int] = None):
+                 mu_mode: Optional[int] = None, sgd_kernel: Optional[int] = None,
+                 waves: Optional[int] = None, _borrowed=None):
+        self._owned = _borrowed is None
+        if _borrowed is not None:
+            self._h = _borrowed
+            self.m, self.n, self.k, self.b = m, n, k, b
+            return
         h = C.c_void_p()
         st = lib.bmf_create(m, n, k, b, C.byref(h))
         if st != 0:
             raise BmfError(st, lib.bmf_last_error(None).decode())
         self._h = h
+        if waves is not None:
+            self.set_option(OPT_WAVES_PER_BLOCK, waves)
         self.m, self.n, self.k, self.b = m, n, k, b
         if seed is not None:
             self.set_option(OPT_SEED, seed)
@@ -112,9 +130,9 @@ class Model:
             raise BmfError(st, lib.bmf_last_error(self._h).decode())
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and getattr(self, "_owned", True):
             lib.bmf_destroy(self._h)
-            self._h = None
+        self._h = None
 
     destroy = close
 
@@ -232,6 +250,68 @@ class Model:
         launches = C.c_int64()
         self._check(lib.bmf_sgd_timing(self._h, C.byref(ms), C.byref(launches), int(reset)))
         return ms.value, launches.value
+
+
+class Batch:
+    """Many problems trained in one persistent launch per epochs call."""
+
+    def __init__(self, shapes, k: int, b=None, seed: Optional[int] = None, order_mode: Optional[int] = None,
+                 order_seed: Optional[int] = None, waves: Optional[int] = None):
+        m = np.array([s[0] for s in shapes], dtype=np.int64)
+        n = np.array([s[1] for s in shapes], dtype=np.int64)
+        bb = None if b is None else np.array(b, dtype=np.int32)
+        h = C.c_void_p()
+        st = lib.bmf_batch_create(len(shapes), _ptr(m), _ptr(n), k, _ptr(bb), C.byref(h))
+        if st != 0:
+            raise BmfError(st, "bmf_batch_create")
+        self._h = h
+        self.m, self.n, self.k = m, n, k
+        for key, val in ((OPT_SEED, seed), (OPT_STRATUM_ORDER, order_mode), (OPT_ORDER_SEED, order_seed),
+                         (OPT_WAVES_PER_BLOCK, waves)):
+            if val is not None:
+                self._check(lib.bmf_batch_set_option(self._h, key, int(val)))
+
+    def _check(self, st: int):
+        if st != 0:
+            raise BmfError(st, lib.bmf_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.bmf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, p: int, u, i, r):
+        u, i, r = _c(u, np.int32), _c(i, np.int32), _c(r, np.float32)
+        self._check(lib.bmf_batch_load(self._h, p, _ptr(u), _ptr(i), _ptr(r), u.shape[0]))
+
+    def tune(self):
+        self._check(lib.bmf_batch_tune(self._h))
+
+    def epochs(self, epochs: int, lr: float = None, reg: float = None, hp=None):
+        hp = _c([lr, reg] * 4 if hp is None else hp, np.float32)
+        self._check(lib.bmf_batch_epochs(self._h, epochs, _ptr(hp)))
+
+    def problem(self, p: int) -> Model:
+        h = C.c_void_p()
+        self._check(lib.bmf_batch_problem(self._h, p, C.byref(h)))
+        b, _, _ = self.info(p)
+        return Model(int(self.m[p]), int(self.n[p]), self.k, b, _borrowed=h)
+
+    def info(self, p: int):
+        b, w, ms = C.c_int32(), C.c_int32(), C.c_double()
+        self._check(lib.bmf_batch_info(self._h, p, C.byref(b), C.byref(w), C.byref(ms)))
+        return b.value, w.value, ms.value
+
+    def timing(self, reset: bool = False):
+        ms, n = C.c_double(), C.c_int64()
+        self._check(lib.bmf_batch_timing(self._h, C.byref(ms), C.byref(n), int(reset)))
+        return ms.value, n.value
 
 
 def stratum_order(b: int, seed: int, epoch: int, mode: int) -> np.ndarray:

@@ -204,9 +204,9 @@ bmf_status bmf_set_option(bmf_ctx *c, int32_t key, int64_t value) {
             if (value < 0 || value > 2) BMF_FAIL(BMF_E_INVAL, "SGD kernel must be 0, 1 or 2");
             M.sgd_kernel = (int)value;
             break;
-        case BMF_OPT_PERSISTENT:
-            if (value != 0 && value != 1) BMF_FAIL(BMF_E_INVAL, "persistent must be 0 or 1");
-            M.persistent = (int)value;
+        case BMF_OPT_WAVES_PER_BLOCK:
+            if (value != 4 && value != 8) BMF_FAIL(BMF_E_INVAL, "waves per block must be 4 or 8");
+            M.waves = (int)value;
             break;
         default: BMF_FAIL(BMF_E_INVAL, "unknown option " + std::to_string(key));
         }

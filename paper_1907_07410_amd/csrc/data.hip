@@ -298,6 +298,23 @@ __global__ void part_finish_kernel(const uint64_t *__restrict__ keys, int64_t nn
     (void)ibits;
 }
 
+void block_histogram(const int32_t *u, const int32_t *i, int64_t nnz, int64_t m, int64_t n, int b,
+                     std::vector<int64_t> &out, hipStream_t s) {
+    const int64_t nb = (int64_t)b * b;
+    const int64_t rb = (m + b - 1) / b, cb = (n + b - 1) / b;
+    DevBuf cnt;
+    cnt.alloc(nb * sizeof(unsigned long long));
+    BMF_HIP(hipMemsetAsync(cnt.p, 0, nb * sizeof(unsigned long long), s));
+    if (nnz > 0) {
+        const int grid = (int)std::min<int64_t>((nnz + 255) / 256, 8192);
+        part_hist_kernel<<<grid, 256, 0, s>>>(u, i, nnz, rb, cb, b, cnt.as<unsigned long long>());
+        BMF_HIP(hipGetLastError());
+    }
+    out.resize(nb);
+    BMF_HIP(hipMemcpyAsync(out.data(), cnt.p, nb * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    BMF_HIP(hipStreamSynchronize(s));
+}
+
 static int bits_for(int64_t count) {  // bits to hold values 0..count-1
     int b = 0;
     while (b < 63 && (1ll << b) < count) ++b;

@@ -39,6 +39,19 @@ struct Rec {
     float r;
 };
 
+struct BatchProblem {
+    const Rec *recs;
+    const int64_t *block_ptr;
+    float *P, *Q, *bu, *bi;
+    int64_t n, rb, cb;
+    float mu;
+    int b, ibits;
+};
+
+struct BatchItem {
+    int32_t p, t, s, j;
+};
+
 // Device buffer owned by a context.
 struct DevBuf {
     void *p = nullptr;
@@ -75,7 +88,7 @@ struct Model {
     int64_t m = 0, n = 0;
     int k = 0, b = 0;
     uint64_t seed = 1001, order_seed = 2001;
-    int order_mode = 0, mu_mode = 0, sgd_kernel = 0, persistent = 0;
+    int order_mode = 0, mu_mode = 0, sgd_kernel = 0, waves = 4;
     DevBuf P, Q, bu, bi;
     double mu = 0.0;
     // training data
@@ -120,12 +133,23 @@ int64_t validate_coo(const int32_t *u, const int32_t *i, const float *r, int64_t
                      int64_t n, DevBuf &scratch, hipStream_t s);
 // FP64 sum of r[0..nnz) in a fixed order (synchronises).
 double sum_f32_as_f64(const float *r, int64_t nnz, DevBuf &scratch, hipStream_t s);
+// Ratings per block of a b x b grid, block id row * b + column (synchronises).
+void block_histogram(const int32_t *u, const int32_t *i, int64_t nnz, int64_t m, int64_t n, int b,
+                     std::vector<int64_t> &out, hipStream_t s);
 // Build a partition (synchronises).
 void build_partition(Partition &out, const int32_t *u, const int32_t *i, const float *r, int64_t nnz,
                      int64_t m, int64_t n, int b, hipStream_t s);
 
 // SGD: run one epoch of strata in `order`.
 void sgd_epoch(Model &M, const int32_t *order, const HP &hp);
+// LDS bytes the LDS-staged kernel needs for a k x cb item slice, and the
+// device's per-workgroup maximum.
+size_t sgd_lds_bytes(int k, int64_t cb);
+int sgd_max_lds(int device);
+// One launch running the blocks items[0 .. count) of several problems
+// (one position of each).
+void sgd_positions_launch(int k, int nw, const BatchProblem *d_probs, const BatchItem *d_items, int64_t count,
+                          const HP &hp, size_t lds, hipStream_t s);
 
 // Evaluation: sum of squared residuals (FP64) over COO, optionally with
 // the regularisation terms (loss). Synchronises.

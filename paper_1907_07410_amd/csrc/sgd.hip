@@ -116,10 +116,7 @@ __global__ __launch_bounds__(64) void sgd_global_kernel(const Rec *__restrict__ 
 //    forwarding of a just-updated item row (two consecutive ratings of the
 //    same item, i.e. a duplicate pair) are selects, and single-lane stores
 //    go through per-lane dummy addresses.
-constexpr int LDS_WG = 256;
 constexpr int CHUNK = 64;
-constexpr int NH = LDS_WG / WAVE - 1;       // helper waves
-constexpr int PER = (CHUNK + NH - 1) / NH;  // records per helper wave
 
 struct LdsLayout {
     size_t q_off, bi_off, rec_off, p_off, bu_off, dummy_off, total;
@@ -145,13 +142,17 @@ __host__ __device__ inline LdsLayout lds_layout(int k, int64_t cb) {
     return L;
 }
 
-template <int KPL, bool FULL>
-__global__ __launch_bounds__(LDS_WG) void sgd_lds_kernel(const Rec *__restrict__ recs,
-                                                         const int64_t *__restrict__ block_ptr, int b, int s,
-                                                         int64_t n, int64_t rb, int64_t cb, int ibits, int k,
-                                                         float *P, float *Q, float *bu, float *bi, float mu,
-                                                         HP hp) {
-    extern __shared__ __align__(16) unsigned char smem[];
+// One block of ratings [beg, end) of the processing order, whose users
+// start at u0 and whose item slice starts at i0.  Called by every thread of
+// a workgroup of NW waves; smem holds lds_layout(k, cb).total bytes.
+template <int KPL, bool FULL, int NW>
+__device__ __forceinline__ void process_block(const Rec *__restrict__ recs, int64_t beg, int64_t end, int64_t u0,
+                                              int64_t i0, int64_t n, int64_t cb, int ibits, int k, float *P,
+                                              float *Q, float *bu, float *bi, float mu, const HP &hp,
+                                              unsigned char *smem) {
+    constexpr int WG = NW * WAVE;
+    constexpr int NH = NW - 1;                  // helper waves
+    constexpr int PER = (CHUNK + NH - 1) / NH;  // record slots per helper wave
     const LdsLayout L = lds_layout(k, cb);
     float *Qs = reinterpret_cast<float *>(smem + L.q_off);
     float *bis = reinterpret_cast<float *>(smem + L.bi_off);
@@ -160,13 +161,7 @@ __global__ __launch_bounds__(LDS_WG) void sgd_lds_kernel(const Rec *__restrict__
     float *bus = reinterpret_cast<float *>(smem + L.bu_off);
     float *dummy = reinterpret_cast<float *>(smem + L.dummy_off);
 
-    const int j = blockIdx.x;
-    const int br = (j + s) % b;
-    const int64_t blk = (int64_t)br * b + j;
-    const int64_t beg = block_ptr[blk], end = block_ptr[blk + 1];
     if (beg == end) return;
-    const int64_t i0 = (int64_t)j * cb;
-    const int64_t u0 = (int64_t)br * rb;
     const int ncols = (int)std::min<int64_t>(cb, n - i0);
     const uint32_t imask = (1u << ibits) - 1u;
     const int tid = threadIdx.x, wave = tid / WAVE, lane = tid % WAVE;
@@ -174,8 +169,8 @@ __global__ __launch_bounds__(LDS_WG) void sgd_lds_kernel(const Rec *__restrict__
     const int nchunks = (int)((cnt + CHUNK - 1) / CHUNK);
 
     // stage the item slice
-    for (int64_t x = tid; x < (int64_t)ncols * k; x += LDS_WG) Qs[x] = Q[i0 * k + x];
-    for (int x = tid; x < ncols; x += LDS_WG) bis[x] = bi[i0 + x];
+    for (int64_t x = tid; x < (int64_t)ncols * k; x += WG) Qs[x] = Q[i0 * k + x];
+    for (int x = tid; x < ncols; x += WG) bis[x] = bi[i0 + x];
 
     // Helper wave hw owns records l = hw + NH*jj of every chunk (the same
     // slots for write-back and staging, so its LDS reads of a slot precede
@@ -363,8 +358,45 @@ __global__ __launch_bounds__(LDS_WG) void sgd_lds_kernel(const Rec *__restrict__
     // the last chunk's runs all end here
     if (wave > 0) write_back(nchunks - 1, 0xffffffffu);
     __syncthreads();
-    for (int64_t x = tid; x < (int64_t)ncols * k; x += LDS_WG) Q[i0 * k + x] = Qs[x];
-    for (int x = tid; x < ncols; x += LDS_WG) bi[i0 + x] = bis[x];
+    for (int64_t x = tid; x < (int64_t)ncols * k; x += WG) Q[i0 * k + x] = Qs[x];
+    for (int x = tid; x < ncols; x += WG) bi[i0 + x] = bis[x];
+}
+
+// One stratum s: workgroup j owns block ((j + s) mod b, j).
+template <int KPL, bool FULL, int NW>
+__global__ __launch_bounds__(NW *WAVE) void sgd_lds_kernel(const Rec *__restrict__ recs,
+                                                           const int64_t *__restrict__ block_ptr, int b, int s,
+                                                           int64_t n, int64_t rb, int64_t cb, int ibits, int k,
+                                                           float *P, float *Q, float *bu, float *bi, float mu,
+                                                           HP hp) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int j = blockIdx.x;
+    const int br = (j + s) % b;
+    const int64_t blk = (int64_t)br * b + j;
+    process_block<KPL, FULL, NW>(recs, block_ptr[blk], block_ptr[blk + 1], (int64_t)br * rb, (int64_t)j * cb, n, cb,
+                                 ibits, k, P, Q, bu, bi, mu, hp, smem);
+}
+
+// ------------------------------------------------------------- batched
+// Many independent problems trained together.  Global position t of problem
+// p is epoch t / b_p, position t % b_p of that epoch's stratum order; one
+// launch runs position t of every problem that has one: workgroup g takes
+// item items[first + g] = (problem, t, stratum s, column j) and runs block
+// ((j + s) mod b_p, j) of that problem.  Blocks of one position of one
+// problem form a stratum (no shared row or column); blocks of different
+// problems share nothing; successive positions are ordered by the stream.
+template <int KPL, bool FULL, int NW>
+__global__ __launch_bounds__(NW *WAVE) void sgd_positions_kernel(const BatchProblem *__restrict__ probs,
+                                                                 const BatchItem *__restrict__ items, int k,
+                                                                 HP hp) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const BatchItem it = items[blockIdx.x];
+    const BatchProblem pr = probs[it.p];
+    const int r = (it.j + it.s) % pr.b;
+    const int64_t blk = (int64_t)r * pr.b + it.j;
+    process_block<KPL, FULL, NW>(pr.recs, pr.block_ptr[blk], pr.block_ptr[blk + 1], (int64_t)r * pr.rb,
+                                 (int64_t)it.j * pr.cb, pr.n, pr.cb, pr.ibits, k, pr.P, pr.Q, pr.bu, pr.bi, pr.mu, hp,
+                                 smem);
 }
 
 // ---------------------------------------------------------------- host
@@ -377,22 +409,28 @@ static void launch_global(Model &M, int s, const HP &hp) {
     BMF_HIP(hipGetLastError());
 }
 
-template <int KPL, bool FULL>
+template <class F>
+static void set_max_lds(F *fn, size_t bytes) {
+    BMF_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+template <int KPL, bool FULL, int NW>
 static void launch_lds(Model &M, int s, const HP &hp, size_t lds_bytes) {
     static size_t attr_done = 0;  // per instantiation
     if (lds_bytes > attr_done) {
-        BMF_HIP(hipFuncSetAttribute((const void *)sgd_lds_kernel<KPL, FULL>,
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+        set_max_lds(sgd_lds_kernel<KPL, FULL, NW>, lds_bytes);
         attr_done = lds_bytes;
     }
     const Partition &Pt = M.part;
-    sgd_lds_kernel<KPL, FULL><<<M.b, LDS_WG, lds_bytes, M.stream>>>(
+    sgd_lds_kernel<KPL, FULL, NW><<<M.b, NW * WAVE, lds_bytes, M.stream>>>(
         Pt.recs.as<Rec>(), Pt.block_ptr.as<int64_t>(), M.b, s, M.n, Pt.rb, Pt.cb, Pt.ibits, M.k, M.P.as<float>(),
         M.Q.as<float>(), M.bu.as<float>(), M.bi.as<float>(), (float)M.mu, hp);
     BMF_HIP(hipGetLastError());
 }
 
-static int max_lds_bytes(int device) {
+size_t sgd_lds_bytes(int k, int64_t cb) { return lds_layout(k, cb).total; }
+
+int sgd_max_lds(int device) {
     static int cached[64] = {0};
     if (device < 64 && cached[device]) return cached[device];
     int v = 0;
@@ -401,19 +439,23 @@ static int max_lds_bytes(int device) {
     return v;
 }
 
+// LDS-staged kernels exist for k <= 128 (one or two factors per lane).
+static bool lds_kernel_ok(int k, int nw) { return k <= 128 && (nw == 4 || nw == 8); }
+
 static void launch_one(Model &M, int s, const HP &hp, int variant, size_t lds) {
     const int kpl = (M.k + WAVE - 1) / WAVE;
     const bool full = M.k == WAVE * kpl;
     if (variant == 2) {
-        switch (kpl * 2 + (full ? 1 : 0)) {
-        case 2: launch_lds<1, false>(M, s, hp, lds); return;
-        case 3: launch_lds<1, true>(M, s, hp, lds); return;
-        case 4: launch_lds<2, false>(M, s, hp, lds); return;
-        case 5: launch_lds<2, true>(M, s, hp, lds); return;
-        case 6: launch_lds<3, false>(M, s, hp, lds); return;
-        case 7: launch_lds<3, true>(M, s, hp, lds); return;
-        case 8: launch_lds<4, false>(M, s, hp, lds); return;
-        case 9: launch_lds<4, true>(M, s, hp, lds); return;
+        const int key = (kpl - 1) * 4 + (full ? 2 : 0) + (M.waves == 8 ? 1 : 0);
+        switch (key) {
+        case 0: launch_lds<1, false, 4>(M, s, hp, lds); return;
+        case 1: launch_lds<1, false, 8>(M, s, hp, lds); return;
+        case 2: launch_lds<1, true, 4>(M, s, hp, lds); return;
+        case 3: launch_lds<1, true, 8>(M, s, hp, lds); return;
+        case 4: launch_lds<2, false, 4>(M, s, hp, lds); return;
+        case 5: launch_lds<2, false, 8>(M, s, hp, lds); return;
+        case 6: launch_lds<2, true, 4>(M, s, hp, lds); return;
+        case 7: launch_lds<2, true, 8>(M, s, hp, lds); return;
         default: break;
         }
     }
@@ -431,20 +473,51 @@ static void launch_one(Model &M, int s, const HP &hp, int variant, size_t lds) {
 }
 
 void sgd_epoch(Model &M, const int32_t *order, const HP &hp) {
-    const int kpl = (M.k + WAVE - 1) / WAVE;
-    const LdsLayout L = lds_layout(M.k, M.part.cb);
-    const bool fits = kpl <= 4 && (int64_t)L.total <= max_lds_bytes(M.device);
+    const size_t lds = sgd_lds_bytes(M.k, M.part.cb);
+    const bool fits = lds_kernel_ok(M.k, M.waves) && (int64_t)lds <= sgd_max_lds(M.device);
     int variant = M.sgd_kernel;
     if (variant == 0) variant = fits ? 2 : 1;
     if (variant == 2 && !fits)
-        BMF_FAIL(BMF_E_STATE, "item slice does not fit in LDS for this block grid; use SGD kernel 1 or a larger b");
+        BMF_FAIL(BMF_E_STATE, "the LDS-staged SGD kernel needs k <= 128 and an item slice that fits in LDS; use "
+                              "SGD kernel 1 or a larger b");
     hipEvent_t ev0 = take_event(M), ev1 = take_event(M);
     BMF_HIP(hipEventRecord(ev0, M.stream));
-    for (int pos = 0; pos < M.b; ++pos) launch_one(M, order[pos], hp, variant, L.total);
+    for (int pos = 0; pos < M.b; ++pos) launch_one(M, order[pos], hp, variant, lds);
     BMF_HIP(hipEventRecord(ev1, M.stream));
     M.pending.emplace_back(ev0, ev1);
     M.sgd_launches += M.b;
     if (M.pending.size() > 64) harvest_timing(M, false);
+}
+
+template <int KPL, bool FULL, int NW>
+static void launch_positions(const BatchProblem *d_probs, const BatchItem *d_items, int64_t count, int k,
+                             const HP &hp, size_t lds, hipStream_t s) {
+    static size_t attr_done = 0;
+    if (lds > attr_done) {
+        set_max_lds(sgd_positions_kernel<KPL, FULL, NW>, lds);
+        attr_done = lds;
+    }
+    sgd_positions_kernel<KPL, FULL, NW><<<(unsigned)count, NW * WAVE, lds, s>>>(d_probs, d_items, k, hp);
+    BMF_HIP(hipGetLastError());
+}
+
+void sgd_positions_launch(int k, int nw, const BatchProblem *d_probs, const BatchItem *d_items, int64_t count,
+                          const HP &hp, size_t lds, hipStream_t s) {
+    if (count == 0) return;
+    if (!lds_kernel_ok(k, nw)) BMF_FAIL(BMF_E_INVAL, "batched training needs k <= 128 and 4 or 8 waves per block");
+    const int kpl = (k + WAVE - 1) / WAVE;
+    const bool full = k == WAVE * kpl;
+    const int key = (kpl - 1) * 4 + (full ? 2 : 0) + (nw == 8 ? 1 : 0);
+    switch (key) {
+    case 0: launch_positions<1, false, 4>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 1: launch_positions<1, false, 8>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 2: launch_positions<1, true, 4>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 3: launch_positions<1, true, 8>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 4: launch_positions<2, false, 4>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 5: launch_positions<2, false, 8>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 6: launch_positions<2, true, 4>(d_probs, d_items, count, k, hp, lds, s); break;
+    default: launch_positions<2, true, 8>(d_probs, d_items, count, k, hp, lds, s); break;
+    }
 }
 
 hipEvent_t take_event(Model &M) {

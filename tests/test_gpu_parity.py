@@ -315,3 +315,18 @@ def test_foldin_matches_oracle(B, orc, k, nr):
     p, bu = G.foldin(items, r, 10, 0.005, 0.05)
     op, obu = orc.foldin(Q, bi, 3.5, items, r, 10, 0.005, 0.05)
     assert np.abs(p - op).max() <= 1e-5 and abs(bu - obu) <= 1e-5
+
+
+@pytest.mark.parametrize("k", [16, 64, 100, 128])
+def test_waves_per_block_do_not_change_results(B, k):
+    rat = synth.random_coo(400, 300, 12000, seed=k, dup=True)
+    outs = []
+    for kernel, waves in ((1, 4), (2, 4), (2, 8)):
+        G = B.Model(400, 300, k, 4, order_mode=1, sgd_kernel=kernel, waves=waves)
+        G.load_ratings(rat.u, rat.i, rat.r)
+        for _ in range(2):
+            G.epoch(0.01, 0.02)
+        outs.append(G.get_factors())
+    for o in outs[1:]:
+        for a, c in zip(outs[0][:4], o[:4]):
+            assert np.array_equal(a.view(np.uint32), c.view(np.uint32))

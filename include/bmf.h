@@ -274,6 +274,66 @@ bmf_status bmf_batch_info(bmf_batch *B, int32_t p, int32_t *b_out, int32_t *wave
  * their launches, ms) and the number of launches. */
 bmf_status bmf_batch_timing(bmf_batch *B, double *ms, int64_t *launches, int32_t reset);
 
+/* -------------------------------------------------------------- serving */
+
+/* Continuous-batching server over a trained context (its factors are read,
+ * never written; do not train the context while a server is open).  A
+ * scheduler thread forms batches from the FIFO queue of submitted requests:
+ * a batch takes requests from the head while their device workspace fits
+ * one batch partition of the memory budget (admission by memory) and the
+ * row cap allows; up to max_batches batches are on the GPU at once on their
+ * own streams, so requests arriving meanwhile go into the next batch while
+ * earlier ones are still running.  Within a batch, fold-in requests run the
+ * fold-in kernel and all rows of a precision are scored in one pass.  Each
+ * row is scored independently, so a request's result is the same whatever
+ * batch it lands in.  The workspace (mem_budget_bytes of device memory and
+ * as much pinned host memory) is allocated at creation; no allocation
+ * happens per request. */
+typedef struct {
+    int64_t mem_budget_bytes;       /* device workspace for in-flight batches (0: 256 MiB) */
+    int32_t max_batches;            /* batches on the GPU at once, 1..4 (0: 2) */
+    int32_t max_batch_rows;         /* users per batch, top-K users plus fold-ins (0: 16384) */
+    int32_t max_requests_per_batch; /* 0: unlimited; 1 turns batching off */
+    int32_t foldin_passes;          /* passes of a fold-in (0: 10) */
+    float foldin_lr, foldin_reg;    /* fold-in step and regulariser (0: 0.005, 0.05) */
+    int32_t Kc;                     /* BF16 candidates per user (0: 2K) */
+} bmf_server_config;
+
+typedef struct {
+    int64_t submitted, completed, rejected, batches, rows;
+    int64_t budget_bytes, peak_bytes, queue_depth;
+    double p50_ms, p90_ms, p99_ms, max_ms, mean_ms; /* submit-to-completion latency */
+} bmf_server_stats;
+
+/* cfg may be NULL (all defaults).  Errors: BMF_E_INVAL (k > 256),
+ * BMF_E_NOMEM, BMF_E_DEVICE. */
+bmf_status bmf_server_create(bmf_ctx *c, const bmf_server_config *cfg, bmf_server **out);
+/* Stops the scheduler (queued requests are dropped, running batches
+ * finish) and frees the workspace. */
+void bmf_server_destroy(bmf_server *S);
+const char *bmf_server_last_error(const bmf_server *S);
+/* Top-K for nu user ids (host array, copied); precision 0 = FP32 MFMA,
+ * 1 = BF16 + FP32 rescore; 1 <= K <= 512.  *id names the request.
+ * Errors: BMF_E_RANGE (bad id), BMF_E_NOMEM (the request alone exceeds a
+ * batch partition; counted as rejected). */
+bmf_status bmf_server_submit_topk(bmf_server *S, const int32_t *users, int32_t nu, int32_t K, int32_t precision,
+                                  int64_t *id);
+/* Fold in a new user from nr (item, rating) pairs (bmf_foldin's update with
+ * the server's passes, lr, reg), then its top-K. */
+bmf_status bmf_server_submit_foldin(bmf_server *S, const int32_t *items, const float *ratings, int32_t nr,
+                                    int32_t K, int32_t precision, int64_t *id);
+/* Result of request id; wait != 0 blocks until it is done.  On done = 1
+ * copies items_out[rows*K], scores_out[rows*K] (rows = nu, or 1 for a
+ * fold-in), p_out[k] and bu_out[1] for fold-ins (any may be NULL) and the
+ * submit-to-completion latency, and forgets the request. */
+bmf_status bmf_server_poll(bmf_server *S, int64_t id, int32_t wait, int32_t *done, int32_t *items_out,
+                           float *scores_out, float *p_out, float *bu_out, int64_t *latency_ns);
+/* Wait until every submitted request is done. */
+bmf_status bmf_server_drain(bmf_server *S);
+/* Counters and latency percentiles (of completed requests since the last
+ * reset). */
+bmf_status bmf_server_get_stats(bmf_server *S, bmf_server_stats *out, int32_t reset);
+
 /* ---------------------------------------------------------- diagnostics */
 
 /* Reduction self-check on the current device: out[0:64], out[64:128],

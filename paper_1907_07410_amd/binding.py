@@ -70,6 +70,14 @@ def _load():
         "bmf_batch_problem": ([p, i32, pp], i32),
         "bmf_batch_info": ([p, i32, p, p, p], i32),
         "bmf_batch_timing": ([p, p, p, i32], i32),
+        "bmf_server_create": ([p, p, pp], i32),
+        "bmf_server_destroy": ([p], None),
+        "bmf_server_last_error": ([p], C.c_char_p),
+        "bmf_server_submit_topk": ([p, p, i32, i32, i32, p], i32),
+        "bmf_server_submit_foldin": ([p, p, p, i32, i32, i32, p], i32),
+        "bmf_server_poll": ([p, i64, i32, p, p, p, p, p, p], i32),
+        "bmf_server_drain": ([p], i32),
+        "bmf_server_get_stats": ([p, p, i32], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -312,6 +320,92 @@ class Batch:
         ms, n = C.c_double(), C.c_int64()
         self._check(lib.bmf_batch_timing(self._h, C.byref(ms), C.byref(n), int(reset)))
         return ms.value, n.value
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("mem_budget_bytes", C.c_int64), ("max_batches", C.c_int32), ("max_batch_rows", C.c_int32),
+                ("max_requests_per_batch", C.c_int32), ("foldin_passes", C.c_int32), ("foldin_lr", C.c_float),
+                ("foldin_reg", C.c_float), ("Kc", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(f, C.c_int64) for f in ("submitted", "completed", "rejected", "batches", "rows", "budget_bytes",
+                                         "peak_bytes", "queue_depth")] + \
+               [(f, C.c_double) for f in ("p50_ms", "p90_ms", "p99_ms", "max_ms", "mean_ms")]
+
+
+class Server:
+    """Continuous-batching server over a trained Model (see bmf_server_*)."""
+
+    def __init__(self, model: Model, mem_budget_bytes: int = 0, max_batches: int = 0, max_batch_rows: int = 0,
+                 max_requests_per_batch: int = 0, foldin_passes: int = 0, foldin_lr: float = 0.0,
+                 foldin_reg: float = 0.0, Kc: int = 0):
+        self.model = model
+        cfg = ServerConfig(mem_budget_bytes, max_batches, max_batch_rows, max_requests_per_batch, foldin_passes,
+                           foldin_lr, foldin_reg, Kc)
+        h = C.c_void_p()
+        st = lib.bmf_server_create(model._h, C.byref(cfg), C.byref(h))
+        if st != 0:
+            raise BmfError(st, lib.bmf_last_error(model._h).decode())
+        self._h = h
+        self._shape = {}
+
+    def _check(self, st: int):
+        if st != 0:
+            raise BmfError(st, lib.bmf_server_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.bmf_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit_topk(self, users, K: int, precision: int = 1) -> int:
+        users = _c(users, np.int32)
+        rid = C.c_int64()
+        self._check(lib.bmf_server_submit_topk(self._h, _ptr(users), users.shape[0], K, precision, C.byref(rid)))
+        self._shape[rid.value] = (users.shape[0], K, False)
+        return rid.value
+
+    def submit_foldin(self, items, ratings, K: int, precision: int = 1) -> int:
+        items, ratings = _c(items, np.int32), _c(ratings, np.float32)
+        rid = C.c_int64()
+        self._check(lib.bmf_server_submit_foldin(self._h, _ptr(items), _ptr(ratings), items.shape[0], K, precision,
+                                                 C.byref(rid)))
+        self._shape[rid.value] = (1, K, True)
+        return rid.value
+
+    def poll(self, rid: int, wait: bool = True):
+        rows, K, fold = self._shape[rid]
+        done = C.c_int32()
+        items = np.zeros((rows, K), dtype=np.int32)
+        scores = np.zeros((rows, K), dtype=np.float32)
+        p = np.zeros(self.model.k, dtype=np.float32) if fold else None
+        bu = np.zeros(1, dtype=np.float32) if fold else None
+        lat = C.c_int64()
+        self._check(lib.bmf_server_poll(self._h, rid, int(wait), C.byref(done), _ptr(items), _ptr(scores), _ptr(p),
+                                        _ptr(bu), C.byref(lat)))
+        if not done.value:
+            return None
+        del self._shape[rid]
+        out = {"items": items, "scores": scores, "latency_ms": lat.value / 1e6}
+        if fold:
+            out["p"] = p
+            out["bu"] = float(bu[0])
+        return out
+
+    def drain(self):
+        self._check(lib.bmf_server_drain(self._h))
+
+    def stats(self, reset: bool = False) -> dict:
+        st = ServerStats()
+        self._check(lib.bmf_server_get_stats(self._h, C.byref(st), int(reset)))
+        return {f: getattr(st, f) for f, _ in st._fields_}
 
 
 def stratum_order(b: int, seed: int, epoch: int, mode: int) -> np.ndarray:

@@ -109,7 +109,7 @@ static int max_lds(int device) {
 }
 
 void foldin_launch(Model &M, const int32_t *d_items, const float *d_r, const int64_t *d_off, int64_t nreq,
-                   int max_cnt, int passes, const HP &hp, float *d_p, int64_t p_stride, float *d_bu) {
+                   int max_cnt, int passes, const HP &hp, float *d_p, int64_t p_stride, float *d_bu, hipStream_t s) {
     if (nreq == 0) return;
     static int lds_cap = 0;
     if (!lds_cap) lds_cap = max_lds(M.device);
@@ -121,7 +121,7 @@ void foldin_launch(Model &M, const int32_t *d_items, const float *d_r, const int
     do {                                                                                                          \
         BMF_HIP(hipFuncSetAttribute((const void *)foldin_kernel<KPL>, hipFuncAttributeMaxDynamicSharedMemorySize, \
                                     lds_cap));                                                                    \
-        foldin_kernel<KPL><<<(unsigned)nreq, FI_WG, lds, M.stream>>>(d_items, d_r, d_off, passes, M.Q.as<float>(),  \
+        foldin_kernel<KPL><<<(unsigned)nreq, FI_WG, lds, s>>>(d_items, d_r, d_off, passes, M.Q.as<float>(),         \
                                                                      M.bi.as<float>(), M.k, (float)M.mu, hp,      \
                                                                      stage_rows, d_p, d_bu, p_stride);            \
     } while (0)
@@ -142,8 +142,37 @@ void foldin_run(Model &M, const int32_t *d_items, const float *d_r, int nr, int 
     off.alloc(2 * sizeof(int64_t));
     const int64_t h[2] = {0, nr};
     BMF_HIP(hipMemcpyAsync(off.p, h, sizeof(h), hipMemcpyHostToDevice, M.stream));
-    foldin_launch(M, d_items, d_r, off.as<int64_t>(), 1, nr, passes, hp, d_p, M.k, d_bu);
+    foldin_launch(M, d_items, d_r, off.as<int64_t>(), 1, nr, passes, hp, d_p, M.k, d_bu, M.stream);
     BMF_HIP(hipStreamSynchronize(M.stream));
+}
+
+__device__ __forceinline__ uint16_t bf16_rne_bits(float x) {
+    uint32_t b = __float_as_uint(x);
+    if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) return (uint16_t)((b >> 16) | 0x40u);
+    b += 0x7fffu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+__global__ void foldin_rows_kernel(const float *__restrict__ bu_f, int64_t nreq, float mu, int k, int kp, int kb,
+                                   float *__restrict__ Ug, uint16_t *__restrict__ Ugb, float *__restrict__ ub) {
+    const int64_t total = nreq * kb;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t q = t / kb;
+        const int f = (int)(t % kb);
+        float v = 0.f;
+        if (f < k) v = Ug[q * kp + f];
+        else if (f < kp) Ug[q * kp + f] = 0.f;
+        if (Ugb) Ugb[q * kb + f] = bf16_rne_bits(v);
+        if (f == 0) ub[q] = mu + bu_f[q];
+    }
+}
+
+void foldin_rows(const float *bu_f, int64_t nreq, float mu, int k, int kp, int kb, float *Ug, uint16_t *Ugb,
+                 float *ub, hipStream_t s) {
+    if (nreq == 0) return;
+    const int grid = (int)std::min<int64_t>((nreq * kb + 255) / 256, 4096);
+    foldin_rows_kernel<<<grid, 256, 0, s>>>(bu_f, nreq, mu, k, kp, kb, Ug, Ugb, ub);
+    BMF_HIP(hipGetLastError());
 }
 
 }  // namespace bmf

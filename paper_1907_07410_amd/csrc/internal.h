@@ -156,13 +156,29 @@ void sgd_positions_launch(int k, int nw, const BatchProblem *d_probs, const Batc
 double sq_residual_sum(const Model &M, const int32_t *u, const int32_t *i, const float *r, int64_t cnt,
                        const HP *loss_hp, DevBuf &scratch);
 
-// Top-K
+// Top-K.  A plan fixes the split of the item range and the workspace
+// layout (user vectors FP32/BF16, per-user offsets mu + bu, candidate
+// lists); gather fills the user vectors from P, score runs selection,
+// merge, rescore and decode.  topk_run does all three on M.stream.
+struct TopkPlan {
+    int64_t nu = 0, nu_pad = 0, per_split = 0;
+    int K = 0, Ksel = 0, kp = 0, kb = 0, S = 1;
+    bool bf = false;
+    size_t off_ug = 0, off_ugb = 0, off_ub = 0, off_part = 0, off_sel = 0, total = 0;
+};
+TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc);
+void topk_gather(Model &M, const TopkPlan &T, const int32_t *d_users, unsigned char *work, hipStream_t s);
+void topk_score(Model &M, const TopkPlan &T, unsigned char *work, int32_t *d_items, float *d_scores, hipStream_t s);
 void topk_run(Model &M, const int32_t *d_users, int64_t nu, int K, int precision, int Kc,
               int32_t *d_items, float *d_scores);
 void foldin_run(Model &M, const int32_t *d_items, const float *d_r, int nr, int passes, const HP &hp,
                 float *d_p, float *d_bu);
 void foldin_launch(Model &M, const int32_t *d_items, const float *d_r, const int64_t *d_off, int64_t nreq,
-                   int max_cnt, int passes, const HP &hp, float *d_p, int64_t p_stride, float *d_bu);
+                   int max_cnt, int passes, const HP &hp, float *d_p, int64_t p_stride, float *d_bu, hipStream_t s);
+// Turn folded-in users (p rows written with stride kp, biases bu_f) into
+// scoring rows: zero the padding, BF16 copy, offset mu + bu.
+void foldin_rows(const float *bu_f, int64_t nreq, float mu, int k, int kp, int kb, float *Ug, uint16_t *Ugb,
+                 float *ub, hipStream_t s);
 void ensure_bf16_items(Model &M);
 
 // Timing: take an event (from the spare list or new), and fold completed

@@ -368,85 +368,78 @@ void ensure_bf16_items(Model &M) {
     M.bf16_valid = true;
 }
 
-// Scratch layout for one top-K call (device bytes).
-struct TopkScratch {
-    size_t ug, ugb, ub, part, sel, total;
-};
-
-static TopkScratch topk_scratch(int64_t nu_pad, int kp, int kb, int S, int Ksel, int K) {
-    TopkScratch T;
+TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
+    TopkPlan T;
+    T.nu = nu;
+    T.K = K;
+    T.bf = precision == 1;
+    if (T.bf && Kc == 0) Kc = 2 * K;
+    if (T.bf && Kc < K) Kc = K;
+    T.Ksel = T.bf ? Kc : K;
+    T.kp = round_up(M.k, 16);
+    T.kb = round_up(M.k, 32);
+    T.nu_pad = (nu + TU - 1) / TU * TU;
+    const int64_t tiles = T.nu_pad / TU;
+    // item splits: enough workgroups to fill the chip, merged afterwards
+    int S = (int)std::max<int64_t>(1, (2048 + tiles - 1) / std::max<int64_t>(tiles, 1));
+    S = (int)std::min<int64_t>(S, std::max<int64_t>(1, M.n / 256));
+    S = std::min(S, std::max(1, MERGE_CAP / T.Ksel));
+    T.per_split = ((M.n + S - 1) / S + TI - 1) / TI * TI;
+    T.S = (int)std::max<int64_t>(1, (M.n + T.per_split - 1) / T.per_split);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
         o += (bytes + 255) & ~size_t(255);
         return at;
     };
-    T.ug = take((size_t)nu_pad * kp * 4);
-    T.ugb = take((size_t)nu_pad * kb * 2);
-    T.ub = take((size_t)nu_pad * 4);
-    T.part = take((size_t)nu_pad * S * Ksel * 8);
-    T.sel = take((size_t)nu_pad * std::max(Ksel, K) * 8);
+    T.off_ug = take((size_t)T.nu_pad * T.kp * 4);
+    T.off_ugb = take((size_t)T.nu_pad * T.kb * 2);
+    T.off_ub = take((size_t)T.nu_pad * 4);
+    T.off_part = take((size_t)T.nu_pad * T.S * T.Ksel * 8);
+    T.off_sel = take((size_t)T.nu_pad * std::max(T.Ksel, T.K) * 8);
     T.total = o;
     return T;
 }
 
-void topk_run(Model &M, const int32_t *d_users, int64_t nu, int K, int precision, int Kc, int32_t *d_items,
-              float *d_scores) {
-    if (nu == 0) return;
-    if (M.k > 256) BMF_FAIL(BMF_E_INVAL, "top-K scoring supports k <= 256");
-    const int kp = round_up(M.k, 16);
-    const int kb = round_up(M.k, 32);
-    const bool bf = precision == 1;
-    if (bf && Kc == 0) Kc = 2 * K;
-    if (bf && Kc < K) Kc = K;
-    const int Ksel = bf ? Kc : K;
-    const int64_t nu_pad = (nu + TU - 1) / TU * TU;
-    const int64_t tiles = nu_pad / TU;
-    // item splits: enough workgroups to fill the chip, merged afterwards
-    int S = (int)std::max<int64_t>(1, (2048 + tiles - 1) / tiles);
-    S = (int)std::min<int64_t>(S, std::max<int64_t>(1, M.n / 256));
-    S = std::min(S, std::max(1, MERGE_CAP / Ksel));
-    const int64_t per_split = ((M.n + S - 1) / S + TI - 1) / TI * TI;
-    S = (int)((M.n + per_split - 1) / per_split);
-    if (S < 1) S = 1;
+void topk_gather(Model &M, const TopkPlan &T, const int32_t *d_users, unsigned char *work, hipStream_t s) {
+    const int grid = (int)std::min<int64_t>((T.nu_pad * T.kb + 255) / 256, 8192);
+    gather_users_kernel<<<grid, 256, 0, s>>>(d_users, T.nu, T.nu_pad, M.m, M.P.as<float>(), M.bu.as<float>(),
+                                            (float)M.mu, M.k, T.kp, T.kb, reinterpret_cast<float *>(work + T.off_ug),
+                                            T.bf ? reinterpret_cast<uint16_t *>(work + T.off_ugb) : nullptr,
+                                            reinterpret_cast<float *>(work + T.off_ub));
+    BMF_HIP(hipGetLastError());
+}
 
-    TopkScratch T = topk_scratch(nu_pad, kp, kb, S, Ksel, K);
-    if (M.scratch.bytes < T.total) M.scratch.alloc(T.total);
-    unsigned char *w = M.scratch.as<unsigned char>();
-    float *Ug = reinterpret_cast<float *>(w + T.ug);
-    uint16_t *Ugb = reinterpret_cast<uint16_t *>(w + T.ugb);
-    float *ub = reinterpret_cast<float *>(w + T.ub);
-    uint64_t *part = reinterpret_cast<uint64_t *>(w + T.part);
-    uint64_t *sel = reinterpret_cast<uint64_t *>(w + T.sel);
-
-    {
-        const int grid = (int)std::min<int64_t>((nu_pad * kb + 255) / 256, 8192);
-        gather_users_kernel<<<grid, 256, 0, M.stream>>>(d_users, nu, nu_pad, M.m, M.P.as<float>(), M.bu.as<float>(),
-                                                        (float)M.mu, M.k, kp, kb, Ug, bf ? Ugb : nullptr, ub);
-        BMF_HIP(hipGetLastError());
+void topk_score(Model &M, const TopkPlan &T, unsigned char *work, int32_t *d_items, float *d_scores, hipStream_t s) {
+    if (T.nu == 0) return;
+    const float *Ug = reinterpret_cast<const float *>(work + T.off_ug);
+    const uint16_t *Ugb = reinterpret_cast<const uint16_t *>(work + T.off_ugb);
+    const float *ub = reinterpret_cast<const float *>(work + T.off_ub);
+    uint64_t *part = reinterpret_cast<uint64_t *>(work + T.off_part);
+    uint64_t *sel = reinterpret_cast<uint64_t *>(work + T.off_sel);
+    const int cap = cap_for(T.Ksel);
+    const dim3 grid((unsigned)(T.nu_pad / TU), (unsigned)T.S);
+    if (T.bf) {
+        if (!M.bf16_valid) BMF_FAIL(BMF_E_STATE, "BF16 item table not prepared");
+        select_dispatch<true>(T.kb / 32, cap, grid, Ug, Ugb, M.Q.as<float>(), M.Qb.as<uint16_t>(), M.bi.as<float>(),
+                              M.n, M.k, T.kp, T.kb, T.Ksel, T.per_split, T.S, part, s);
+    } else {
+        select_dispatch<false>(T.kp / 16, cap, grid, Ug, Ugb, M.Q.as<float>(), nullptr, M.bi.as<float>(), M.n, M.k,
+                               T.kp, T.kb, T.Ksel, T.per_split, T.S, part, s);
     }
-    if (bf) ensure_bf16_items(M);
-    const int cap = cap_for(Ksel);
-    const dim3 grid((unsigned)tiles, (unsigned)S);
-    if (bf)
-        select_dispatch<true>(kb / 32, cap, grid, Ug, Ugb, M.Q.as<float>(), M.Qb.as<uint16_t>(), M.bi.as<float>(),
-                              M.n, M.k, kp, kb, Ksel, per_split, S, part, M.stream);
-    else
-        select_dispatch<false>(kp / 16, cap, grid, Ug, Ugb, M.Q.as<float>(), nullptr, M.bi.as<float>(), M.n, M.k, kp,
-                               kb, Ksel, per_split, S, part, M.stream);
     const uint64_t *cand = part;
-    if (S > 1) {
-        merge_kernel<<<(unsigned)nu, MERGE_WG, 0, M.stream>>>(part, S, Ksel, Ksel, sel);
+    if (T.S > 1) {
+        merge_kernel<<<(unsigned)T.nu, MERGE_WG, 0, s>>>(part, T.S, T.Ksel, T.Ksel, sel);
         BMF_HIP(hipGetLastError());
         cand = sel;
     }
     const uint64_t *fin = cand;
-    if (bf) {
+    if (T.bf) {
         uint64_t *dst = (cand == sel) ? part : sel;
         const int kpl = (M.k + 63) / 64;
-#define RS_LAUNCH(KPL)                                                                                         \
-    rescore_kernel<KPL><<<(unsigned)nu, 64, 0, M.stream>>>(cand, Ksel, K, Ug, kp, M.Q.as<float>(), M.bi.as<float>(), \
-                                                           M.k, dst)
+#define RS_LAUNCH(KPL)                                                                                              \
+    rescore_kernel<KPL><<<(unsigned)T.nu, 64, 0, s>>>(cand, T.Ksel, T.K, Ug, T.kp, M.Q.as<float>(), M.bi.as<float>(), \
+                                                      M.k, dst)
         switch (kpl) {
         case 1: RS_LAUNCH(1); break;
         case 2: RS_LAUNCH(2); break;
@@ -457,9 +450,21 @@ void topk_run(Model &M, const int32_t *d_users, int64_t nu, int K, int precision
         BMF_HIP(hipGetLastError());
         fin = dst;
     }
-    const int dgrid = (int)std::min<int64_t>((nu * K + 255) / 256, 8192);
-    decode_kernel<<<dgrid, 256, 0, M.stream>>>(fin, nu, K, ub, d_items, d_scores);
+    const int dgrid = (int)std::min<int64_t>((T.nu * T.K + 255) / 256, 8192);
+    decode_kernel<<<dgrid, 256, 0, s>>>(fin, T.nu, T.K, ub, d_items, d_scores);
     BMF_HIP(hipGetLastError());
+}
+
+void topk_run(Model &M, const int32_t *d_users, int64_t nu, int K, int precision, int Kc, int32_t *d_items,
+              float *d_scores) {
+    if (nu == 0) return;
+    if (M.k > 256) BMF_FAIL(BMF_E_INVAL, "top-K scoring supports k <= 256");
+    const TopkPlan T = topk_plan(M, nu, K, precision, Kc);
+    if (M.scratch.bytes < T.total) M.scratch.alloc(T.total);
+    unsigned char *w = M.scratch.as<unsigned char>();
+    topk_gather(M, T, d_users, w, M.stream);
+    if (T.bf) ensure_bf16_items(M);
+    topk_score(M, T, w, d_items, d_scores, M.stream);
 }
 
 }  // namespace bmf

@@ -1,0 +1,127 @@
+"""Serving engine: results are the same alone and in a mix, equal the
+direct top-K and fold-in calls, admission respects the memory budget, and a
+Poisson run completes with latency statistics."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1907_07410_amd import serving, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1907_07410_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def model(B):
+    m, n, k = 20000, 6000, 128
+    P, Q, bu, bi, mu = synth.serving_factors(m, n, k, seed=3)
+    G = B.Model(m, n, k, 4)
+    G.set_factors(P, Q, bu, bi, mu)
+    return G, (P, Q, bu, bi, mu)
+
+
+def same(a, b):
+    return np.array_equal(a["items"], b["items"]) and np.array_equal(a["scores"].view(np.uint32),
+                                                                     b["scores"].view(np.uint32))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_alone_equals_in_mix(B, model, precision):
+    G, (P, Q, bu, bi, mu) = model
+    S = B.Server(G, max_batches=2)
+    rng = np.random.default_rng(precision)
+    probe_u = rng.integers(0, G.m, 37).astype(np.int32)
+    probe_items = rng.choice(G.n, 60, replace=False).astype(np.int32)
+    probe_r = rng.integers(1, 6, 60).astype(np.float32)
+    a = S.poll(S.submit_topk(probe_u, 100, precision))
+    af = S.poll(S.submit_foldin(probe_items, probe_r, 50, precision))
+    reqs = serving.make_stream(rng, 40, 0, G.m, G.n, Q, bi, mu)
+    ids = []
+    for q, r in enumerate(reqs):
+        if q == 17:
+            pid = S.submit_topk(probe_u, 100, precision)
+            fid = S.submit_foldin(probe_items, probe_r, 50, precision)
+        if r.kind == "topk":
+            ids.append(S.submit_topk(r.users, 100, 1 - precision if q % 3 == 0 else precision))
+        else:
+            ids.append(S.submit_foldin(r.items, r.ratings, 100, precision))
+    b = S.poll(pid)
+    bf = S.poll(fid)
+    for rid in ids:
+        S.poll(rid)
+    st = S.stats()
+    log("mix stats", {k2: st[k2] for k2 in ("batches", "rows", "completed", "p50_ms", "p99_ms")})
+    assert st["batches"] < st["completed"]  # requests shared batches
+    assert same(a, b)
+    assert same(af, bf) and np.array_equal(af["p"].view(np.uint32), bf["p"].view(np.uint32))
+    S.close()
+
+
+def test_server_matches_direct_calls(B, model):
+    G, _ = model
+    S = B.Server(G)
+    rng = np.random.default_rng(9)
+    users = rng.integers(0, G.m, 300).astype(np.int32)
+    for precision, direct in ((0, G.topk), (1, G.topk_bf16)):
+        r = S.poll(S.submit_topk(users, 100, precision))
+        di, ds = direct(users, 100)
+        assert np.array_equal(r["items"], di)
+        assert np.array_equal(r["scores"].view(np.uint32), ds.view(np.uint32))
+    items = rng.choice(G.n, 200, replace=False).astype(np.int32)
+    rat = rng.integers(1, 6, 200).astype(np.float32)
+    r = S.poll(S.submit_foldin(items, rat, 100, 0))
+    p, bu = G.foldin(items, rat, 10, 0.005, 0.05)
+    assert np.array_equal(r["p"].view(np.uint32), p.view(np.uint32)) and r["bu"] == bu
+    S.close()
+
+
+def test_admission_by_memory(B, model):
+    G, (P, Q, bu, bi, mu) = model
+    budget = 64 << 20
+    S = B.Server(G, mem_budget_bytes=budget, max_batches=2)
+    with pytest.raises(B.BmfError) as ex:
+        S.submit_topk(np.zeros(4000, np.int32), 100, 1)  # larger than one batch partition
+    assert ex.value.status == B.BMF_E_NOMEM
+    rng = np.random.default_rng(5)
+    reqs = serving.make_stream(rng, 60, 0, G.m, G.n, Q, bi, mu, batch_range=(1, 600))
+    ids = [S.submit_topk(r.users, 100, 1) if r.kind == "topk" else S.submit_foldin(r.items, r.ratings, 100, 1)
+           for r in reqs]
+    S.drain()
+    for rid in ids:
+        assert S.poll(rid, wait=False) is not None
+    st = S.stats()
+    log("admission stats", st)
+    assert st["rejected"] == 1 and st["completed"] == 60
+    assert 0 < st["peak_bytes"] <= st["budget_bytes"] <= budget
+    S.close()
+
+
+def test_unbatched_configuration_runs_one_request_per_batch(B, model):
+    G, (P, Q, bu, bi, mu) = model
+    S = B.Server(G, max_batches=1, max_requests_per_batch=1)
+    rng = np.random.default_rng(6)
+    reqs = serving.make_stream(rng, 20, 0, G.m, G.n, Q, bi, mu, batch_range=(1, 256))
+    st = serving.run(S, reqs, K=100, precision=0)
+    assert st["batches"] == 20 and st["completed"] == 20
+    S.close()
+
+
+def test_poisson_run_reports_latency(B, model):
+    G, (P, Q, bu, bi, mu) = model
+    S = B.Server(G, max_batches=2)
+    rng = np.random.default_rng(7)
+    reqs = serving.make_stream(rng, 200, 400.0, G.m, G.n, Q, bi, mu, batch_range=(1, 512))
+    st = serving.run(S, reqs, K=100, precision=1)
+    log("poisson", {k2: st[k2] for k2 in ("req_per_s", "p50_ms", "p99_ms", "batches", "completed")})
+    assert st["completed"] == 200 and 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+    S.close()

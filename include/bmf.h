@@ -72,12 +72,17 @@ typedef enum {
     /* hipStream_t (cast to int64) on which all work is enqueued; 0 = the
      * context's own stream. */
     BMF_OPT_STREAM = 4,
-    /* SGD kernel: 0 = automatic, 1 = global-memory reference kernel,
-     * 2 = LDS-staged item slice kernel.  All produce the same update
-     * sequence; the value only changes speed. */
+    /* SGD kernel: 0 = automatic (2 when the load built a plan, else 1),
+     * 1 = global-memory reference kernel running each block's ratings in
+     * (u, i, t) order, 2 = LDS-staged planned kernel: the block's item slice
+     * and its active users' rows in LDS, four independent ratings per step
+     * (a list schedule built at load time that reorders only ratings sharing
+     * neither user nor item).  For k <= 128, 1 and 2 give identical bits;
+     * 2 needs k <= 128 and an item slice that leaves room in LDS for at
+     * least 8 user slots (BMF_E_STATE otherwise). */
     BMF_OPT_SGD_KERNEL = 5,
     /* waves per workgroup of the LDS-staged SGD kernel: 4 or 8 (one wave
-     * runs the update chain, the others stage data); default 4.  On a
+     * runs the update steps, the others stage data); default 4.  On a
      * batch, 0 lets the autotuner choose.  Does not change results. */
     BMF_OPT_WAVES_PER_BLOCK = 6
 } bmf_option;
@@ -115,8 +120,10 @@ bmf_status bmf_synchronize(bmf_ctx *c);
  * 0 <= i < n and finite r (BMF_E_RANGE names the first bad index), computes
  * mu, and partitions the ratings into the b x b blocks on the device: block
  * (u / rb, i / cb), visited inside a block in (u, i, t) order (Algorithm 2's
- * row and column loops).  Replaces previously loaded ratings; keeps the
- * factors.  nnz may be 0 (then u, i, r may be NULL).
+ * row and column loops); then builds the LDS kernel's per-block step plan
+ * on the host (the partition is copied back for it).  Replaces previously
+ * loaded ratings; keeps the factors.  nnz may be 0 (then u, i, r may be
+ * NULL).
  * Errors: BMF_E_INVAL, BMF_E_RANGE (also when a block's local (row, column)
  * needs more than 32 bits: use a larger b), BMF_E_NOMEM, BMF_E_DEVICE. */
 bmf_status bmf_load_ratings(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r,
@@ -335,6 +342,23 @@ bmf_status bmf_server_drain(bmf_server *S);
 bmf_status bmf_server_get_stats(bmf_server *S, bmf_server_stats *out, int32_t reset);
 
 /* ---------------------------------------------------------- diagnostics */
+
+/* Host-only: the step plan the LDS-staged SGD kernel follows for one block
+ * (no device needed).  u_local[x], i_local[x], r[x], x < n: the block's
+ * ratings in processing order ((u, i) non-decreasing, BMF_E_INVAL
+ * otherwise), 0 <= i_local < cb < 65536 and u_local < 2^(32 - bits(cb))
+ * (BMF_E_RANGE otherwise); slots = LDS user slots (1..4095), chunk = steps
+ * per chunk (>= 1).  *n_steps receives the number of steps.  When out is
+ * non-null it receives 4 records per step, 4 uint32 words each: {meta,
+ * rating bits, u_local, x} with meta = i_local | slot << 16 | 1 << 30 (the
+ * user's first rating) | 1 << 31 (its last); an empty record has
+ * i_local = cb, slot = slots and x = 0xffffffff.  Ratings of one step share
+ * no user and no item; every user's and every item's ratings keep their
+ * order; a slot freed in chunk a is next used in chunk a + 3 or later.
+ * BMF_E_RANGE when out is non-null and max_steps is smaller than the plan. */
+bmf_status bmf_debug_block_plan(int64_t n, const int32_t *u_local, const int32_t *i_local, const float *r,
+                                int32_t cb, int32_t slots, int32_t chunk, int64_t max_steps, int64_t *n_steps,
+                                uint32_t *out);
 
 /* Reduction self-check on the current device: out[0:64], out[64:128],
  * out[128:192] and out[192:256] receive, per lane, the 64-lane sum of

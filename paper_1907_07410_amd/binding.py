@@ -59,6 +59,7 @@ def _load():
         "bmf_foldin": ([p, p, p, i32, i32, f32, f32, p, p], i32),
         "bmf_sgd_timing": ([p, p, p, i32], i32),
         "bmf_debug_wave_sum": ([p, p], i32),
+        "bmf_debug_block_plan": ([i64, p, p, p, i32, i32, i32, i64, p, p], i32),
         "bmf_stratum_order": ([i32, C.c_uint64, i32, i32, p], i32),
         "bmf_batch_create": ([i32, p, p, i32, p, pp], i32),
         "bmf_batch_destroy": ([p], None),
@@ -413,6 +414,29 @@ def stratum_order(b: int, seed: int, epoch: int, mode: int) -> np.ndarray:
     st = lib.bmf_stratum_order(b, seed, epoch, mode, _ptr(out))
     if st != 0:
         raise BmfError(st, "bmf_stratum_order")
+    return out
+
+
+PLAN_FIRST = 1 << 30
+PLAN_LAST = 1 << 31
+
+
+def block_plan(u_local, i_local, r, cb: int, slots: int, chunk: int) -> np.ndarray:
+    """Step plan of one block (host only): uint32 array (steps, 4, 4) of
+    {meta, rating bits, u_local, index} records (see bmf_debug_block_plan)."""
+    u_local = _c(u_local, np.int32)
+    i_local = _c(i_local, np.int32)
+    r = _c(r, np.float32)
+    n = len(u_local)
+    ns = np.zeros(1, dtype=np.int64)
+    st = lib.bmf_debug_block_plan(n, _ptr(u_local), _ptr(i_local), _ptr(r), cb, slots, chunk, 0, _ptr(ns), None)
+    if st != 0:
+        raise BmfError(st, lib.bmf_last_error(None).decode())
+    out = np.zeros((int(ns[0]), 4, 4), dtype=np.uint32)
+    st = lib.bmf_debug_block_plan(n, _ptr(u_local), _ptr(i_local), _ptr(r), cb, slots, chunk, int(ns[0]), _ptr(ns),
+                                  _ptr(out))
+    if st != 0:
+        raise BmfError(st, lib.bmf_last_error(None).decode())
     return out
 
 

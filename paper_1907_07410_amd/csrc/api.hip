@@ -86,6 +86,8 @@ void load_common(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r,
     if (M.mu_mode == 0 && nnz > 0) mu = sum_f32_as_f64(dr.as<float>(), nnz, M.red, M.stream) / (double)nnz;
     Partition P;
     build_partition(P, du.as<int32_t>(), di.as<int32_t>(), dr.as<float>(), nnz, M.m, M.n, M.b, M.stream);
+    Plan plan;
+    build_plan(plan, P, M.b, M.k, sgd_max_lds(M.device), M.stream);
     // commit
     M.cu.swap(du);
     M.ci.swap(di);
@@ -99,6 +101,7 @@ void load_common(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r,
     M.part.cb = P.cb;
     M.part.ibits = P.ibits;
     M.part.ubits = P.ubits;
+    M.plan.swap(plan);
     M.mu = mu;
     M.loaded = true;
     M.bf16_valid = false;
@@ -424,6 +427,40 @@ bmf_status bmf_sgd_timing(bmf_ctx *c, double *ms, int64_t *launches, int32_t res
             M.sgd_launches = 0;
         }
     });
+}
+
+bmf_status bmf_debug_block_plan(int64_t n, const int32_t *u_local, const int32_t *i_local, const float *r,
+                                int32_t cb, int32_t slots, int32_t chunk, int64_t max_steps, int64_t *n_steps,
+                                uint32_t *out) {
+    if (n < 0 || (n > 0 && (!u_local || !i_local || !r)) || !n_steps || cb < 1 || cb >= (1 << 16) || slots < 1 ||
+        slots > bmf::PLAN_MAX_SLOTS || chunk < 1)
+        return BMF_E_INVAL;
+    int ibits = 0;
+    while ((1 << ibits) < cb) ++ibits;
+    try {
+        std::vector<uint32_t> ui(n);
+        for (int64_t x = 0; x < n; ++x) {
+            if (u_local[x] < 0 || (ibits > 0 && (uint64_t)u_local[x] >= (1ull << (32 - ibits))) || i_local[x] < 0 ||
+                i_local[x] >= cb)
+                return BMF_E_RANGE;
+            if (x > 0 && (u_local[x] < u_local[x - 1] || (u_local[x] == u_local[x - 1] && i_local[x] < i_local[x - 1])))
+                return BMF_E_INVAL;
+            ui[x] = ((uint32_t)u_local[x] << ibits) | (uint32_t)i_local[x];
+        }
+        std::vector<bmf::SlotRec> recs;
+        const int64_t st = bmf::plan_block(ui.data(), r, n, ibits, cb, slots, chunk, recs);
+        *n_steps = st;
+        if (out) {
+            if (max_steps < st) return BMF_E_RANGE;
+            std::memcpy(out, recs.data(), recs.size() * sizeof(bmf::SlotRec));
+        }
+    } catch (const bmf::Error &e) {
+        g_create_error = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        return BMF_E_NOMEM;
+    }
+    return BMF_OK;
 }
 
 bmf_status bmf_debug_wave_sum(const float *in64, float *out256) {

@@ -78,7 +78,8 @@ bool grid_ok(int64_t m, int64_t n, int k, int b, int device) {
     while ((1ll << ub) < rb) ++ub;
     while ((1ll << ib) < cb) ++ib;
     if (ub + ib > 32) return false;
-    return (int64_t)sgd_lds_bytes(k, cb) <= sgd_max_lds(device);
+    const int kp = plan_kp(k);
+    return kp && cb + 1 <= (1 << 16) && plan_slots(kp, cb, PLAN_CH, sgd_max_lds(device)) >= PLAN_MIN_SLOTS;
 }
 
 double model_ms(const Coef &c, const Candidate &x, int k) {
@@ -439,10 +440,11 @@ bmf_status bmf_batch_epochs(bmf_batch *B, int32_t epochs, const float hp[8]) {
         size_t lds = 0;
         for (int p = 0; p < np; ++p) {
             Model &M = B->probs[p]->M;
-            tab[p] = BatchProblem{M.part.recs.as<Rec>(), M.part.block_ptr.as<int64_t>(), M.P.as<float>(),
+            if (!M.plan.ok) BMF_FAIL(BMF_E_STATE, "problem " + std::to_string(p) + " has no plan for the LDS kernel");
+            tab[p] = BatchProblem{M.plan.steps.as<SlotRec>(), M.plan.blk_step.as<int64_t>(), M.P.as<float>(),
                                   M.Q.as<float>(), M.bu.as<float>(), M.bi.as<float>(), M.n, M.part.rb, M.part.cb,
-                                  (float)M.mu, M.b, M.part.ibits};
-            lds = std::max(lds, sgd_lds_bytes(B->k, M.part.cb));
+                                  (float)M.mu, M.b, M.plan.S, M.plan.CH};
+            lds = std::max(lds, plan_lds(M.plan.kp, M.part.cb, M.plan.S, M.plan.CH).total);
         }
         // work list, position-major: the items of position t are contiguous
         int64_t maxT = 0;

@@ -39,13 +39,59 @@ struct Rec {
     float r;
 };
 
+// One rating slot of a plan step (16 bytes): meta = item_local | slot << 16
+// | FIRST | LAST (FIRST: the user's first rating in the block, its row is
+// loaded into the slot before the step's chunk; LAST: its final rating,
+// the slot is written back after the step's chunk), the rating, the user's
+// local row, and the rating's index inside the block (all ones for an
+// empty slot).
+struct SlotRec {
+    uint32_t meta;
+    float r;
+    uint32_t ul;
+    uint32_t idx;
+};
+constexpr int PLAN_W = 4;            // ratings per step (16-lane groups of one wavefront)
+constexpr int PLAN_CH = 16;          // steps per chunk
+constexpr int PLAN_MAX_HELPERS = 7;  // helper wavefronts per workgroup, at most
+constexpr int PLAN_MAX_SLOTS = 4095;
+constexpr int PLAN_MIN_SLOTS = 8;
+constexpr uint32_t PLAN_SLOT_MASK = 0x3fffu;
+constexpr uint32_t PLAN_FIRST = 1u << 30, PLAN_LAST = 1u << 31;
+
+// LDS layout of the planned kernel: item slice (cb + 1 rows of kp floats,
+// the last one a dummy for empty slots), item biases, three chunks of slot
+// records, per-helper compaction lists, S + 1 user slots (slot S the
+// dummy) and their biases.
+struct PlanLds {
+    size_t q, bi, rec, scr, u, bu, total;
+};
+__host__ __device__ inline PlanLds plan_lds(int kp, int64_t cb, int S, int CH) {
+    PlanLds L;
+    size_t o = 0;
+    L.q = o;
+    o += (size_t)(cb + 1) * kp * 4;
+    L.bi = o;
+    o += (size_t)((cb + 1 + 3) / 4) * 16;
+    L.rec = o;
+    o += (size_t)3 * CH * PLAN_W * sizeof(SlotRec);
+    L.scr = o;
+    o += (size_t)PLAN_MAX_HELPERS * 64 * 8;
+    L.u = o;
+    o += (size_t)(S + 1) * kp * 4;
+    L.bu = o;
+    o += (size_t)((S + 1 + 3) / 4) * 16;
+    L.total = o;
+    return L;
+}
+
 struct BatchProblem {
-    const Rec *recs;
-    const int64_t *block_ptr;
+    const SlotRec *steps;
+    const int64_t *blk_step;
     float *P, *Q, *bu, *bi;
     int64_t n, rb, cb;
     float mu;
-    int b, ibits;
+    int b, S, CH;
 };
 
 struct BatchItem {
@@ -80,6 +126,26 @@ struct Partition {
     std::vector<int64_t> h_block_ptr;
 };
 
+// Execution plan of the LDS-staged SGD kernel (see plan.hip).
+struct Plan {
+    bool ok = false;
+    int kp = 0, S = 0, CH = PLAN_CH;
+    int64_t total_steps = 0;
+    DevBuf steps;     // SlotRec[total_steps * PLAN_W]
+    DevBuf blk_step;  // int64[b*b + 1], step offsets per block
+    std::vector<int64_t> h_blk_step;
+    void swap(Plan &o) {
+        std::swap(ok, o.ok);
+        std::swap(kp, o.kp);
+        std::swap(S, o.S);
+        std::swap(CH, o.CH);
+        std::swap(total_steps, o.total_steps);
+        steps.swap(o.steps);
+        blk_step.swap(o.blk_step);
+        h_blk_step.swap(o.h_blk_step);
+    }
+};
+
 // --------------------------------------------------------------- context
 struct Model {
     int device = 0;
@@ -95,6 +161,7 @@ struct Model {
     bool loaded = false;
     DevBuf cu, ci, cr;  // training COO as given (int32, int32, f32)
     Partition part;
+    Plan plan;
     int32_t epoch = 0;
     // bf16 copies for scoring
     DevBuf Pb, Qb;
@@ -140,14 +207,23 @@ void block_histogram(const int32_t *u, const int32_t *i, int64_t nnz, int64_t m,
 void build_partition(Partition &out, const int32_t *u, const int32_t *i, const float *r, int64_t nnz,
                      int64_t m, int64_t n, int b, hipStream_t s);
 
+// Plans: LDS row length for k factors (16 lanes x 1, 2, 4 or 8 floats; 0
+// when k > 128), user slots that fit next to a cb-row item slice, one
+// block's schedule (host; returns the step count, appends PLAN_W records
+// per step), and the whole partition's plan (leaves out.ok false when the
+// planned kernel does not apply).
+int plan_kp(int k);
+int plan_slots(int kp, int64_t cb, int CH, int max_lds);
+int64_t plan_block(const uint32_t *ui, const float *r, int64_t n, int ibits, int cb, int S, int CH,
+                   std::vector<SlotRec> &out);
+void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hipStream_t s);
+
 // SGD: run one epoch of strata in `order`.
 void sgd_epoch(Model &M, const int32_t *order, const HP &hp);
-// LDS bytes the LDS-staged kernel needs for a k x cb item slice, and the
-// device's per-workgroup maximum.
-size_t sgd_lds_bytes(int k, int64_t cb);
+// The device's per-workgroup LDS maximum.
 int sgd_max_lds(int device);
 // One launch running the blocks items[0 .. count) of several problems
-// (one position of each).
+// (one position of each) with the planned kernel.
 void sgd_positions_launch(int k, int nw, const BatchProblem *d_probs, const BatchItem *d_items, int64_t count,
                           const HP &hp, size_t lds, hipStream_t s);
 

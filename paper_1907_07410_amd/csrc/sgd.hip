@@ -7,10 +7,15 @@
 // disjoint rows of P/bu and of Q/bi; the stream order between launches is
 // the barrier between strata.
 //
-// Inside a block one wavefront walks the ratings in (u, i, t) order; lane f
-// owns latent factors f, f + 64, ... .  Every variant below performs the
-// same floating-point operations in the same order (the helpers below), so all
-// variants produce identical bits.
+// Inside a block the ratings are updated in (u, i, t) order (Algorithm 2),
+// or in a plan's steps, which reorder only ratings that share neither user
+// nor item and so give the same bits.  For k <= 128 a rating is handled by
+// 16 lanes (lane l owns factors l*F .. l*F + F - 1, F = 1, 2, 4 or 8) and
+// both kernels that use this layout perform the same floating-point
+// operations in the same order (the helpers below): the reference kernel
+// (global memory, processing order) and the planned LDS kernel agree bit for
+// bit.  For k > 128 the reference kernel spreads a rating over all 64 lanes
+// (lane f owns factors f, f + 64, ...).
 #pragma clang fp contract(off)
 
 #include <algorithm>
@@ -53,8 +58,9 @@ __device__ __forceinline__ float residual(float r, float mu, float bu0, float bi
     return (((r - mu) - bu0) - bi0) - dot;
 }
 
-// ---------------------------------------------------------------- v0
-// Reference kernel: every value read from and written to global memory.
+// ---------------------------------------------------------- v0, k > 128
+// Reference kernel for k > 128: every value read from and written to global
+// memory, one wavefront per block.
 template <int KPL>
 __global__ __launch_bounds__(64) void sgd_global_kernel(const Rec *__restrict__ recs,
                                                         const int64_t *__restrict__ block_ptr, int b, int s,
@@ -96,285 +102,288 @@ __global__ __launch_bounds__(64) void sgd_global_kernel(const Rec *__restrict__ 
     }
 }
 
-// ---------------------------------------------------------------- v1
-// LDS-staged kernel.  Workgroup = 4 waves: wave 0 runs the dependent
-// update chain, waves 1-3 move data.
-//  * The block column's item slice Q[i0 : i0+cb] and bi slice live in LDS
-//    for the whole block (read once, written back once).
-//  * Ratings go in chunks of 64.  While wave 0 works on chunk c, the helper
-//    waves (a) write back to global memory the user rows whose run ended in
-//    chunk c-1 and (b) stage chunk c+1: its records and, for every record
-//    that starts a user run, that user's P row and bu, into the other half
-//    of a double buffer.  One barrier per chunk.
-//  * Wave 0 touches no global memory: it keeps the current user's p and bu
-//    in registers (a user's ratings are contiguous in (u, i) order), reads
-//    the next rating's item row, item bias and (possibly new) user row from
-//    LDS one rating ahead, and after every rating writes the updated item
-//    row and bias back to the slice and the updated user row and bias to
-//    the rating's staging slot, where the helpers find the final values of
-//    each run.  The loop body has no branches: run switches and the
-//    forwarding of a just-updated item row (two consecutive ratings of the
-//    same item, i.e. a duplicate pair) are selects, and single-lane stores
-//    go through per-lane dummy addresses.
-constexpr int CHUNK = 64;
-
-struct LdsLayout {
-    size_t q_off, bi_off, rec_off, p_off, bu_off, dummy_off, total;
-};
-
-__host__ __device__ inline LdsLayout lds_layout(int k, int64_t cb) {
-    LdsLayout L;
-    size_t o = 0;
-    L.q_off = o;
-    o += (size_t)cb * k * 4;
-    L.bi_off = o;
-    o += (size_t)cb * 4 + 64 * 4 * 4;  // slack: full-width reads of the last row stay inside
-    o = (o + 15) & ~size_t(15);
-    L.rec_off = o;
-    o += 3 * CHUNK * sizeof(Rec);  // records: triple buffer (wave 0 reads c, helpers read c-1, write c+1)
-    L.p_off = o;
-    o += (size_t)2 * CHUNK * k * 4 + 64 * 4 * 4;
-    L.bu_off = o;
-    o += 2 * CHUNK * 4;
-    L.dummy_off = o;
-    o += 64 * 16 * 4;
-    L.total = o;
-    return L;
+// ------------------------------------------------------------ v0, k <= 128
+// Reference kernel in the 16-lane layout the planned kernel uses: one
+// 16-lane row per block (a workgroup of 64 threads runs four blocks of the
+// stratum), lane l owns factors l*F .. l*F + F - 1, everything in global
+// memory, ratings in processing order.  Its arithmetic is the planned
+// kernel's, so the two agree bit for bit.
+template <int F>
+__global__ __launch_bounds__(64) void sgd_ref16_kernel(const Rec *__restrict__ recs,
+                                                       const int64_t *__restrict__ block_ptr, int b, int s,
+                                                       int64_t rb, int64_t cb, int ibits, int k, float *P, float *Q,
+                                                       float *bu, float *bi, float mu, HP hp) {
+    const int row = threadIdx.x >> 4, gl = threadIdx.x & 15;
+    const int j = blockIdx.x * 4 + row;
+    if (j >= b) return;
+    const int br = (j + s) % b;
+    const int64_t blk = (int64_t)br * b + j;
+    const int64_t beg = block_ptr[blk], end = block_ptr[blk + 1];
+    const uint32_t imask = (1u << ibits) - 1u;
+    for (int64_t t = beg; t < end; ++t) {
+        const Rec rec = recs[t];
+        const int64_t u = (int64_t)br * rb + (rec.ui >> ibits);
+        const int64_t i = (int64_t)j * cb + (rec.ui & imask);
+        float p[F], q[F];
+#pragma unroll
+        for (int c = 0; c < F; ++c) {
+            const int f = gl * F + c;
+            p[c] = f < k ? P[u * k + f] : 0.f;
+            q[c] = f < k ? Q[i * k + f] : 0.f;
+        }
+        const float dot = row16_sum(lane_dot(p, q));
+        const float bu0 = bu[u], bi0 = bi[i];
+        const float e = residual(rec.r, mu, bu0, bi0, dot);
+        factor_update(p, q, e, hp);
+#pragma unroll
+        for (int c = 0; c < F; ++c) {
+            const int f = gl * F + c;
+            if (f < k) {
+                P[u * k + f] = p[c];
+                Q[i * k + f] = q[c];
+            }
+        }
+        if (gl == 0) {
+            bu[u] = bias_update(bu0, e, hp.a_bu, hp.b_bu);
+            bi[i] = bias_update(bi0, e, hp.a_bi, hp.b_bi);
+        }
+    }
 }
 
-// One block of ratings [beg, end) of the processing order, whose users
-// start at u0 and whose item slice starts at i0.  Called by every thread of
-// a workgroup of NW waves; smem holds lds_layout(k, cb).total bytes.
-template <int KPL, bool FULL, int NW>
-__device__ __forceinline__ void process_block(const Rec *__restrict__ recs, int64_t beg, int64_t end, int64_t u0,
-                                              int64_t i0, int64_t n, int64_t cb, int ibits, int k, float *P,
+// ---------------------------------------------------------------- v1
+// Planned LDS kernel.  A block's ratings run in the steps of its plan
+// (plan.hip): four mutually independent ratings per step, one per 16-lane
+// group of wavefront 0, which touches only LDS:
+//  * the block column's item slice (Q rows and bi) is staged once and
+//    written back once;
+//  * every user active in the block has an LDS slot holding p_u and bu_u;
+//  * per step each group reads its slot record (item, slot, rating), its
+//    user and item rows, does the update of Eqs 10-13 with the dot product
+//    summed over its 16 lanes, and writes both rows back.  Empty slots point
+//    at a dummy user slot and a dummy item row.
+// The other wavefronts are helpers.  Steps go in chunks of CH; while
+// wavefront 0 runs chunk c the helpers write back to global memory the user
+// rows whose last rating was in chunk c-1 and stage chunk c+1: its slot
+// records and the rows of users whose first rating is in it.  The plan
+// keeps a slot idle for two chunks between its users, so these never touch
+// a slot wavefront 0 is using.  One barrier per chunk; records are triple
+// buffered (chunk c-1 read by the write-back, c by the chain, c+1 staged).
+template <int F>
+__device__ __forceinline__ void row_ld(float (&v)[F], const float *a) {
+    if constexpr (F == 1) {
+        v[0] = a[0];
+    } else if constexpr (F == 2) {
+        const float2 t = *reinterpret_cast<const float2 *>(a);
+        v[0] = t.x;
+        v[1] = t.y;
+    } else {
+#pragma unroll
+        for (int c = 0; c < F; c += 4) {
+            const float4 t = *reinterpret_cast<const float4 *>(a + c);
+            v[c] = t.x;
+            v[c + 1] = t.y;
+            v[c + 2] = t.z;
+            v[c + 3] = t.w;
+        }
+    }
+}
+
+template <int F>
+__device__ __forceinline__ void row_st(float *a, const float (&v)[F]) {
+    if constexpr (F == 1) {
+        a[0] = v[0];
+    } else if constexpr (F == 2) {
+        *reinterpret_cast<float2 *>(a) = make_float2(v[0], v[1]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < F; c += 4) *reinterpret_cast<float4 *>(a + c) = make_float4(v[c], v[c + 1], v[c + 2], v[c + 3]);
+    }
+}
+
+__device__ __forceinline__ int lane_rank(uint64_t mask) {
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <int F, bool VEC, int NW>
+__device__ __forceinline__ void planned_block(const SlotRec *__restrict__ steps, int64_t nsteps, int64_t u0,
+                                              int64_t i0, int64_t n, int64_t cb, int k, int S, int CH, float *P,
                                               float *Q, float *bu, float *bi, float mu, const HP &hp,
                                               unsigned char *smem) {
+    constexpr int KP = 16 * F;
     constexpr int WG = NW * WAVE;
-    constexpr int NH = NW - 1;                  // helper waves
-    constexpr int PER = (CHUNK + NH - 1) / NH;  // record slots per helper wave
-    const LdsLayout L = lds_layout(k, cb);
-    float *Qs = reinterpret_cast<float *>(smem + L.q_off);
-    float *bis = reinterpret_cast<float *>(smem + L.bi_off);
-    Rec *rbuf = reinterpret_cast<Rec *>(smem + L.rec_off);
-    float *Ps = reinterpret_cast<float *>(smem + L.p_off);
-    float *bus = reinterpret_cast<float *>(smem + L.bu_off);
-    float *dummy = reinterpret_cast<float *>(smem + L.dummy_off);
-
-    if (beg == end) return;
+    constexpr int NH = NW - 1;
+    constexpr int RB = 2;  // rows in flight per 16-lane group while staging
+    if (nsteps <= 0) return;
+    const PlanLds L = plan_lds(KP, cb, S, CH);
+    float *Qs = reinterpret_cast<float *>(smem + L.q);
+    float *Bis = reinterpret_cast<float *>(smem + L.bi);
+    SlotRec *Rb = reinterpret_cast<SlotRec *>(smem + L.rec);
+    uint2 *Scr = reinterpret_cast<uint2 *>(smem + L.scr);
+    float *Us = reinterpret_cast<float *>(smem + L.u);
+    float *Bus = reinterpret_cast<float *>(smem + L.bu);
     const int ncols = (int)std::min<int64_t>(cb, n - i0);
-    const uint32_t imask = (1u << ibits) - 1u;
     const int tid = threadIdx.x, wave = tid / WAVE, lane = tid % WAVE;
-    const int64_t cnt = end - beg;
-    const int nchunks = (int)((cnt + CHUNK - 1) / CHUNK);
+    const int g = lane >> 4, gl = lane & 15;
+    const int RPC = CH * PLAN_W;
+    const int nch = (int)((nsteps + CH - 1) / CH);
 
-    // stage the item slice
-    for (int64_t x = tid; x < (int64_t)ncols * k; x += WG) Qs[x] = Q[i0 * k + x];
-    for (int x = tid; x < ncols; x += WG) bis[x] = bi[i0 + x];
+    // item slice (zero beyond k), dummy item row and dummy user slot
+    for (int64_t x = tid; x < (int64_t)ncols * KP; x += WG) {
+        const int64_t il = x / KP;
+        const int f = (int)(x % KP);
+        Qs[x] = f < k ? Q[(i0 + il) * k + f] : 0.f;
+    }
+    for (int x = tid; x < ncols; x += WG) Bis[x] = bi[i0 + x];
+    if (tid < KP) {
+        Qs[(size_t)cb * KP + tid] = 0.f;
+        Us[(size_t)S * KP + tid] = 0.f;
+    }
+    if (tid == 0) {
+        Bis[cb] = 0.f;
+        Bus[S] = 0.f;
+    }
 
-    // Helper wave hw owns records l = hw + NH*jj of every chunk (the same
-    // slots for write-back and staging, so its LDS reads of a slot precede
-    // its writes in program order).
     const int hw = wave - 1;
-    const int lj = hw + NH * lane;  // this lane's record slot
+    uint2 *scr = Scr + (size_t)(hw < 0 ? 0 : hw) * WAVE;
 
-    // write back the user rows whose run ended in chunk c (buffer c & 1);
-    // `next_ul` is the local user of the record after the chunk (or ~0)
-    auto write_back = [&](int c, uint32_t next_ul) {
-        const int buf = c & 1;
-        const Rec *rb3 = rbuf + (c % 3) * CHUNK;
-        const int64_t cbeg = beg + (int64_t)c * CHUNK;
-        const int len = (int)std::min<int64_t>(CHUNK, end - cbeg);
-        const bool valid = lane < PER && lj < len;
-        uint32_t ul = 0, ul_next = next_ul;
-        if (valid) {
-            ul = rb3[lj].ui >> ibits;
-            if (lj + 1 < len) ul_next = rb3[lj + 1].ui >> ibits;
-        }
-        const bool run_end = valid && ul_next != ul;
-        if (run_end) bu[u0 + ul] = bus[buf * CHUNK + lj];
-        const uint64_t emask = __ballot(run_end);
+    // helpers: write back the users whose last rating is in chunk c
+    auto write_back = [&](int c) {
+        const int cnt = (int)std::min<int64_t>(CH, nsteps - (int64_t)c * CH) * PLAN_W;
+        const SlotRec *src = Rb + (size_t)(c % 3) * RPC;
+        for (int base = 0; base < cnt; base += NH * WAVE) {
+            const int x = base + lane * NH + hw;
+            const bool valid = x < cnt;
+            SlotRec rec{0u, 0.f, 0u, 0u};
+            if (valid) rec = src[x];
+            const bool last = valid && (rec.meta & PLAN_LAST);
+            const uint64_t mask = __ballot(last);
+            const int nl = __popcll(mask);
+            if (last) scr[lane_rank(mask)] = make_uint2(rec.ul, (rec.meta >> 16) & PLAN_SLOT_MASK);
+            for (int e = g; e < nl; e += 4) {
+                const uint2 en = scr[e];
+                const int64_t row = u0 + en.x;
+                float v[F];
+                row_ld<F>(v, Us + (size_t)en.y * KP + gl * F);
+                if (VEC) {
+                    row_st<F>(P + row * k + gl * F, v);
+                } else {
 #pragma unroll
-        for (int jj = 0; jj < PER; ++jj) {
-            if ((emask >> jj) & 1ull) {
-                const int l = hw + NH * jj;
-                const int64_t urow = u0 + (int64_t)__builtin_amdgcn_readlane(ul, jj);
-#pragma unroll
-                for (int cc = 0; cc < KPL; ++cc) {
-                    const int f = lane + WAVE * cc;
-                    if (FULL || f < k) P[urow * k + f] = Ps[((size_t)buf * CHUNK + l) * k + f];
+                    for (int c2 = 0; c2 < F; ++c2)
+                        if (gl * F + c2 < k) P[row * k + gl * F + c2] = v[c2];
                 }
+                if (gl == 0) bu[row] = Bus[en.y];
             }
         }
     };
-
-    // stage chunk c into buffer c & 1: every P row a run starts with is
-    // loaded into registers before any is written, so the loads overlap
+    // helpers: stage chunk c (records, and the rows of users starting in it)
     auto stage = [&](int c) {
-        const int buf = c & 1;
-        const int64_t cbeg = beg + (int64_t)c * CHUNK;
-        const int len = (int)std::min<int64_t>(CHUNK, end - cbeg);
-        const bool valid = lane < PER && lj < len;
-        uint32_t ui = 0, uprev = 0xffffffffu;
-        float rr = 0.f;
-        if (valid) {
-            const Rec rc = recs[cbeg + lj];
-            ui = rc.ui;
-            rr = rc.r;
-            if (lj > 0) uprev = recs[cbeg + lj - 1].ui >> ibits;
-        }
-        const uint32_t ul = ui >> ibits;
-        const bool start = valid && (lj == 0 || uprev != ul);
-        const float buv = start ? bu[u0 + ul] : 0.f;
-        const uint64_t smask = __ballot(start);
-        float v[PER][KPL];
+        const int64_t s0 = (int64_t)c * CH;
+        const int cnt = (int)std::min<int64_t>(CH, nsteps - s0) * PLAN_W;
+        SlotRec *dst = Rb + (size_t)(c % 3) * RPC;
+        const SlotRec *src = steps + s0 * PLAN_W;
+        for (int base = 0; base < cnt; base += NH * WAVE) {
+            const int x = base + lane * NH + hw;
+            const bool valid = x < cnt;
+            SlotRec rec{0u, 0.f, 0u, 0u};
+            if (valid) rec = src[x];
+            const bool first = valid && (rec.meta & PLAN_FIRST);
+            if (valid) dst[x] = rec;
+            const uint64_t mask = __ballot(first);
+            const int nf = __popcll(mask);
+            if (first) scr[lane_rank(mask)] = make_uint2(rec.ul, (rec.meta >> 16) & PLAN_SLOT_MASK);
+            for (int e0 = 0; e0 < nf; e0 += 4 * RB) {
+                float v[RB][F];
+                float bv[RB];
+                uint32_t sl[RB];
 #pragma unroll
-        for (int jj = 0; jj < PER; ++jj) {
-            if ((smask >> jj) & 1ull) {
-                const int64_t urow = u0 + (int64_t)__builtin_amdgcn_readlane(ul, jj);
+                for (int jj = 0; jj < RB; ++jj) {
+                    const int e = e0 + 4 * jj + g;
+                    sl[jj] = 0xffffffffu;
+                    bv[jj] = 0.f;
 #pragma unroll
-                for (int cc = 0; cc < KPL; ++cc) {
-                    const int f = lane + WAVE * cc;
-                    v[jj][cc] = (FULL || f < k) ? P[urow * k + f] : 0.f;
+                    for (int c2 = 0; c2 < F; ++c2) v[jj][c2] = 0.f;
+                    if (e < nf) {
+                        const uint2 en = scr[e];
+                        sl[jj] = en.y;
+                        const int64_t row = u0 + en.x;
+                        if (VEC) {
+                            row_ld<F>(v[jj], P + row * k + gl * F);
+                        } else {
+#pragma unroll
+                            for (int c2 = 0; c2 < F; ++c2)
+                                if (gl * F + c2 < k) v[jj][c2] = P[row * k + gl * F + c2];
+                        }
+                        bv[jj] = bu[row];
+                    }
                 }
-            }
-        }
-        if (valid) {
-            rbuf[(c % 3) * CHUNK + lj] = Rec{ui, rr - mu};  // the rating minus mu, as every kernel forms it first
-            if (start) bus[buf * CHUNK + lj] = buv;
-        }
 #pragma unroll
-        for (int jj = 0; jj < PER; ++jj) {
-            if ((smask >> jj) & 1ull) {
-                const int l = hw + NH * jj;
-#pragma unroll
-                for (int cc = 0; cc < KPL; ++cc) {
-                    const int f = lane + WAVE * cc;
-                    if (FULL || f < k) Ps[((size_t)buf * CHUNK + l) * k + f] = v[jj][cc];
+                for (int jj = 0; jj < RB; ++jj) {
+                    if (sl[jj] != 0xffffffffu) {
+                        row_st<F>(Us + (size_t)sl[jj] * KP + gl * F, v[jj]);
+                        Bus[sl[jj]] = bv[jj];
+                    }
                 }
             }
         }
     };
+
     if (wave > 0) stage(0);
     __syncthreads();
-
-    // wave 0 state carried across chunks
-    float p[KPL], q_upd[KPL];
-#pragma unroll
-    for (int cc = 0; cc < KPL; ++cc) p[cc] = q_upd[cc] = 0.f;
-    float bu_cur = 0.f, bi_upd = 0.f;
-    uint32_t cur_ul = 0xffffffffu;
-
-    for (int c = 0; c < nchunks; ++c) {
-        const int buf = c & 1;
-        if (wave > 0) {
-            if (c > 0) {
-                const uint32_t nxt = rbuf[(c % 3) * CHUNK].ui >> ibits;  // first record of chunk c
-                write_back(c - 1, nxt);
-            }
-            if (c + 1 < nchunks) stage(c + 1);
-        } else {
-            const int64_t cbeg = beg + (int64_t)c * CHUNK;
-            const int len = __builtin_amdgcn_readfirstlane((int)std::min<int64_t>(CHUNK, end - cbeg));
-            const Rec myrec = rbuf[(c % 3) * CHUNK + lane];  // slots past len hold stale records, never used
-            const uint32_t rec_ui = myrec.ui;
-            const float rec_r = myrec.r;
-            float *Pbuf = Ps + (size_t)buf * CHUNK * k;
-            float *Bbuf = bus + buf * CHUNK;
-
-            // rating 0 of the chunk: item row and bias (the slice already
-            // holds every earlier update), staged user row
-            uint32_t ui_n = __builtin_amdgcn_readlane(rec_ui, 0);
-            float r_n = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rec_r), 0));
-            float qn[KPL], pn[KPL];
-#pragma unroll
-            for (int cc = 0; cc < KPL; ++cc) {
-                const int f = lane + WAVE * cc;
-                const float a = Qs[(ui_n & imask) * k + f];
-                const float bb = Pbuf[f];
-                qn[cc] = (FULL || f < k) ? a : 0.f;
-                pn[cc] = (FULL || f < k) ? bb : 0.f;
-            }
-            float bin = bis[ui_n & imask];
-            float bun = Bbuf[0];
-            bool same_item = false;
-            bool new_user = (ui_n >> ibits) != cur_ul;
-
-            for (int l = 0; l < len; ++l) {
-                const uint32_t ui = ui_n;
-                const uint32_t il = ui & imask;
-                const float r = r_n;
-                float q[KPL];
-#pragma unroll
-                for (int cc = 0; cc < KPL; ++cc) {
-                    q[cc] = same_item ? q_upd[cc] : qn[cc];
-                    p[cc] = new_user ? pn[cc] : p[cc];
-                }
-                const float bi0 = same_item ? bi_upd : bin;
-                const float bu0 = new_user ? bun : bu_cur;
-                // one rating ahead
-                const int ln = (l + 1 < len) ? l + 1 : l;
-                ui_n = __builtin_amdgcn_readlane(rec_ui, ln);
-                r_n = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(rec_r), ln));
-#pragma unroll
-                for (int cc = 0; cc < KPL; ++cc) {
-                    const int f = lane + WAVE * cc;
-                    const float a = Qs[(ui_n & imask) * k + f];
-                    const float bb = Pbuf[(size_t)ln * k + f];
-                    qn[cc] = (FULL || f < k) ? a : 0.f;
-                    pn[cc] = (FULL || f < k) ? bb : 0.f;
-                }
-                bin = bis[ui_n & imask];
-                bun = Bbuf[ln];
-                same_item = (ui_n & imask) == il;
-                new_user = (ui_n >> ibits) != (ui >> ibits);
-                // the update (same operations as the reference kernel)
-                const float cres = (r - bu0) - bi0;  // r already holds rating - mu
-                const float dot = wave_sum_perm(lane_dot(p, q));
-                const float e = cres - dot;
+    for (int c = 0; c < nch; ++c) {
+        if (wave == 0) {
+            const SlotRec *rb = Rb + (size_t)(c % 3) * RPC;
+            const int len = (int)std::min<int64_t>(CH, nsteps - (int64_t)c * CH);
+            uint2 nx = *reinterpret_cast<const uint2 *>(&rb[g]);
+            for (int t = 0; t < len; ++t) {
+                const uint32_t meta = nx.x;
+                const float r = __uint_as_float(nx.y);
+                const int tn = t + 1 < len ? t + 1 : t;
+                nx = *reinterpret_cast<const uint2 *>(&rb[tn * PLAN_W + g]);
+                const uint32_t il = meta & 0xffffu, us = (meta >> 16) & PLAN_SLOT_MASK;
+                float *pr = Us + (size_t)us * KP + gl * F;
+                float *qr = Qs + (size_t)il * KP + gl * F;
+                float p[F], q[F];
+                row_ld<F>(p, pr);
+                row_ld<F>(q, qr);
+                const float bu0 = Bus[us], bi0 = Bis[il];
+                const float dot = row16_sum(lane_dot(p, q));
+                const float e = residual(r, mu, bu0, bi0, dot);
                 factor_update(p, q, e, hp);
-                bi_upd = bias_update(bi0, e, hp.a_bi, hp.b_bi);
-                bu_cur = bias_update(bu0, e, hp.a_bu, hp.b_bu);
-#pragma unroll
-                for (int cc = 0; cc < KPL; ++cc) {
-                    const int f = lane + WAVE * cc;
-                    q_upd[cc] = q[cc];
-                    float *qa = (FULL || f < k) ? &Qs[il * k + f] : &dummy[lane];
-                    float *pa = (FULL || f < k) ? &Pbuf[(size_t)l * k + f] : &dummy[lane];
-                    *qa = q[cc];
-                    *pa = p[cc];
-                }
-                {
-                    float *ba = lane == 0 ? &bis[il] : &dummy[lane];
-                    float *ua = lane == 0 ? &Bbuf[l] : &dummy[64 + lane];
-                    *ba = bi_upd;
-                    *ua = bu_cur;
-                }
+                row_st<F>(pr, p);
+                row_st<F>(qr, q);
+                Bus[us] = bias_update(bu0, e, hp.a_bu, hp.b_bu);
+                Bis[il] = bias_update(bi0, e, hp.a_bi, hp.b_bi);
             }
-            cur_ul = __builtin_amdgcn_readlane(rec_ui, len - 1) >> ibits;
+        } else {
+            if (c > 0) write_back(c - 1);
+            if (c + 1 < nch) stage(c + 1);
         }
         __syncthreads();
     }
-    // the last chunk's runs all end here
-    if (wave > 0) write_back(nchunks - 1, 0xffffffffu);
+    if (wave > 0) write_back(nch - 1);
     __syncthreads();
-    for (int64_t x = tid; x < (int64_t)ncols * k; x += WG) Q[i0 * k + x] = Qs[x];
-    for (int x = tid; x < ncols; x += WG) bi[i0 + x] = bis[x];
+    for (int64_t x = tid; x < (int64_t)ncols * KP; x += WG) {
+        const int64_t il = x / KP;
+        const int f = (int)(x % KP);
+        if (f < k) Q[(i0 + il) * k + f] = Qs[x];
+    }
+    for (int x = tid; x < ncols; x += WG) bi[i0 + x] = Bis[x];
 }
 
 // One stratum s: workgroup j owns block ((j + s) mod b, j).
-template <int KPL, bool FULL, int NW>
-__global__ __launch_bounds__(NW *WAVE) void sgd_lds_kernel(const Rec *__restrict__ recs,
-                                                           const int64_t *__restrict__ block_ptr, int b, int s,
-                                                           int64_t n, int64_t rb, int64_t cb, int ibits, int k,
-                                                           float *P, float *Q, float *bu, float *bi, float mu,
-                                                           HP hp) {
+template <int F, bool VEC, int NW>
+__global__ __launch_bounds__(NW *WAVE) void sgd_plan_kernel(const SlotRec *__restrict__ steps,
+                                                            const int64_t *__restrict__ blk_step, int b, int s,
+                                                            int64_t n, int64_t rb, int64_t cb, int k, int S, int CH,
+                                                            float *P, float *Q, float *bu, float *bi, float mu,
+                                                            HP hp) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int j = blockIdx.x;
     const int br = (j + s) % b;
     const int64_t blk = (int64_t)br * b + j;
-    process_block<KPL, FULL, NW>(recs, block_ptr[blk], block_ptr[blk + 1], (int64_t)br * rb, (int64_t)j * cb, n, cb,
-                                 ibits, k, P, Q, bu, bi, mu, hp, smem);
+    const int64_t s0 = blk_step[blk];
+    planned_block<F, VEC, NW>(steps + s0 * PLAN_W, blk_step[blk + 1] - s0, (int64_t)br * rb, (int64_t)j * cb, n, cb,
+                              k, S, CH, P, Q, bu, bi, mu, hp, smem);
 }
 
 // ------------------------------------------------------------- batched
@@ -385,7 +394,7 @@ __global__ __launch_bounds__(NW *WAVE) void sgd_lds_kernel(const Rec *__restrict
 // ((j + s) mod b_p, j) of that problem.  Blocks of one position of one
 // problem form a stratum (no shared row or column); blocks of different
 // problems share nothing; successive positions are ordered by the stream.
-template <int KPL, bool FULL, int NW>
+template <int F, bool VEC, int NW>
 __global__ __launch_bounds__(NW *WAVE) void sgd_positions_kernel(const BatchProblem *__restrict__ probs,
                                                                  const BatchItem *__restrict__ items, int k,
                                                                  HP hp) {
@@ -394,9 +403,10 @@ __global__ __launch_bounds__(NW *WAVE) void sgd_positions_kernel(const BatchProb
     const BatchProblem pr = probs[it.p];
     const int r = (it.j + it.s) % pr.b;
     const int64_t blk = (int64_t)r * pr.b + it.j;
-    process_block<KPL, FULL, NW>(pr.recs, pr.block_ptr[blk], pr.block_ptr[blk + 1], (int64_t)r * pr.rb,
-                                 (int64_t)it.j * pr.cb, pr.n, pr.cb, pr.ibits, k, pr.P, pr.Q, pr.bu, pr.bi, pr.mu, hp,
-                                 smem);
+    const int64_t s0 = pr.blk_step[blk];
+    planned_block<F, VEC, NW>(pr.steps + s0 * PLAN_W, pr.blk_step[blk + 1] - s0, (int64_t)r * pr.rb,
+                              (int64_t)it.j * pr.cb, pr.n, pr.cb, k, pr.S, pr.CH, pr.P, pr.Q, pr.bu, pr.bi, pr.mu,
+                              hp, smem);
 }
 
 // ---------------------------------------------------------------- host
@@ -409,26 +419,34 @@ static void launch_global(Model &M, int s, const HP &hp) {
     BMF_HIP(hipGetLastError());
 }
 
-template <class F>
-static void set_max_lds(F *fn, size_t bytes) {
-    BMF_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-}
-
-template <int KPL, bool FULL, int NW>
-static void launch_lds(Model &M, int s, const HP &hp, size_t lds_bytes) {
-    static size_t attr_done = 0;  // per instantiation
-    if (lds_bytes > attr_done) {
-        set_max_lds(sgd_lds_kernel<KPL, FULL, NW>, lds_bytes);
-        attr_done = lds_bytes;
-    }
+template <int F>
+static void launch_ref16(Model &M, int s, const HP &hp) {
     const Partition &Pt = M.part;
-    sgd_lds_kernel<KPL, FULL, NW><<<M.b, NW * WAVE, lds_bytes, M.stream>>>(
-        Pt.recs.as<Rec>(), Pt.block_ptr.as<int64_t>(), M.b, s, M.n, Pt.rb, Pt.cb, Pt.ibits, M.k, M.P.as<float>(),
-        M.Q.as<float>(), M.bu.as<float>(), M.bi.as<float>(), (float)M.mu, hp);
+    sgd_ref16_kernel<F><<<(M.b + 3) / 4, 64, 0, M.stream>>>(Pt.recs.as<Rec>(), Pt.block_ptr.as<int64_t>(), M.b, s,
+                                                           Pt.rb, Pt.cb, Pt.ibits, M.k, M.P.as<float>(),
+                                                           M.Q.as<float>(), M.bu.as<float>(), M.bi.as<float>(),
+                                                           (float)M.mu, hp);
     BMF_HIP(hipGetLastError());
 }
 
-size_t sgd_lds_bytes(int k, int64_t cb) { return lds_layout(k, cb).total; }
+template <class K>
+static void set_max_lds(K *fn, size_t bytes) {
+    BMF_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+}
+
+template <int F, bool VEC, int NW>
+static void launch_plan(Model &M, int s, const HP &hp) {
+    const size_t lds = plan_lds(16 * F, M.part.cb, M.plan.S, M.plan.CH).total;
+    static size_t attr_done = 0;  // per instantiation
+    if (lds > attr_done) {
+        set_max_lds(sgd_plan_kernel<F, VEC, NW>, lds);
+        attr_done = lds;
+    }
+    sgd_plan_kernel<F, VEC, NW><<<M.b, NW * WAVE, lds, M.stream>>>(
+        M.plan.steps.as<SlotRec>(), M.plan.blk_step.as<int64_t>(), M.b, s, M.n, M.part.rb, M.part.cb, M.k,
+        M.plan.S, M.plan.CH, M.P.as<float>(), M.Q.as<float>(), M.bu.as<float>(), M.bi.as<float>(), (float)M.mu, hp);
+    BMF_HIP(hipGetLastError());
+}
 
 int sgd_max_lds(int device) {
     static int cached[64] = {0};
@@ -439,29 +457,42 @@ int sgd_max_lds(int device) {
     return v;
 }
 
-// LDS-staged kernels exist for k <= 128 (one or two factors per lane).
-static bool lds_kernel_ok(int k, int nw) { return k <= 128 && (nw == 4 || nw == 8); }
+// dispatch key of the planned kernels: F in {1, 2, 4, 8}, k == 16 F, waves
+static int plan_key(int k, int nw) {
+    const int kp = plan_kp(k);
+    const int fi = kp == 16 ? 0 : kp == 32 ? 1 : kp == 64 ? 2 : 3;
+    return fi * 4 + (k == kp ? 2 : 0) + (nw == 8 ? 1 : 0);
+}
 
-static void launch_one(Model &M, int s, const HP &hp, int variant, size_t lds) {
-    const int kpl = (M.k + WAVE - 1) / WAVE;
-    const bool full = M.k == WAVE * kpl;
+static void launch_one(Model &M, int s, const HP &hp, int variant) {
     if (variant == 2) {
-        const int key = (kpl - 1) * 4 + (full ? 2 : 0) + (M.waves == 8 ? 1 : 0);
-        switch (key) {
-        case 0: launch_lds<1, false, 4>(M, s, hp, lds); return;
-        case 1: launch_lds<1, false, 8>(M, s, hp, lds); return;
-        case 2: launch_lds<1, true, 4>(M, s, hp, lds); return;
-        case 3: launch_lds<1, true, 8>(M, s, hp, lds); return;
-        case 4: launch_lds<2, false, 4>(M, s, hp, lds); return;
-        case 5: launch_lds<2, false, 8>(M, s, hp, lds); return;
-        case 6: launch_lds<2, true, 4>(M, s, hp, lds); return;
-        case 7: launch_lds<2, true, 8>(M, s, hp, lds); return;
-        default: break;
+        switch (plan_key(M.k, M.waves)) {
+        case 0: launch_plan<1, false, 4>(M, s, hp); return;
+        case 1: launch_plan<1, false, 8>(M, s, hp); return;
+        case 2: launch_plan<1, true, 4>(M, s, hp); return;
+        case 3: launch_plan<1, true, 8>(M, s, hp); return;
+        case 4: launch_plan<2, false, 4>(M, s, hp); return;
+        case 5: launch_plan<2, false, 8>(M, s, hp); return;
+        case 6: launch_plan<2, true, 4>(M, s, hp); return;
+        case 7: launch_plan<2, true, 8>(M, s, hp); return;
+        case 8: launch_plan<4, false, 4>(M, s, hp); return;
+        case 9: launch_plan<4, false, 8>(M, s, hp); return;
+        case 10: launch_plan<4, true, 4>(M, s, hp); return;
+        case 11: launch_plan<4, true, 8>(M, s, hp); return;
+        case 12: launch_plan<8, false, 4>(M, s, hp); return;
+        case 13: launch_plan<8, false, 8>(M, s, hp); return;
+        case 14: launch_plan<8, true, 4>(M, s, hp); return;
+        default: launch_plan<8, true, 8>(M, s, hp); return;
         }
     }
-    switch (kpl) {
-    case 1: launch_global<1>(M, s, hp); break;
-    case 2: launch_global<2>(M, s, hp); break;
+    switch (plan_kp(M.k)) {
+    case 16: launch_ref16<1>(M, s, hp); return;
+    case 32: launch_ref16<2>(M, s, hp); return;
+    case 64: launch_ref16<4>(M, s, hp); return;
+    case 128: launch_ref16<8>(M, s, hp); return;
+    default: break;
+    }
+    switch ((M.k + WAVE - 1) / WAVE) {
     case 3: launch_global<3>(M, s, hp); break;
     case 4: launch_global<4>(M, s, hp); break;
     case 5: launch_global<5>(M, s, hp); break;
@@ -473,42 +504,38 @@ static void launch_one(Model &M, int s, const HP &hp, int variant, size_t lds) {
 }
 
 void sgd_epoch(Model &M, const int32_t *order, const HP &hp) {
-    const size_t lds = sgd_lds_bytes(M.k, M.part.cb);
-    const bool fits = lds_kernel_ok(M.k, M.waves) && (int64_t)lds <= sgd_max_lds(M.device);
     int variant = M.sgd_kernel;
-    if (variant == 0) variant = fits ? 2 : 1;
-    if (variant == 2 && !fits)
-        BMF_FAIL(BMF_E_STATE, "the LDS-staged SGD kernel needs k <= 128 and an item slice that fits in LDS; use "
-                              "SGD kernel 1 or a larger b");
+    if (variant == 0) variant = M.plan.ok ? 2 : 1;
+    if (variant == 2 && !M.plan.ok)
+        BMF_FAIL(BMF_E_STATE, "the LDS-staged SGD kernel needs k <= 128 and an item slice that leaves room for "
+                              "user slots in LDS; use SGD kernel 1 or a larger b");
     hipEvent_t ev0 = take_event(M), ev1 = take_event(M);
     BMF_HIP(hipEventRecord(ev0, M.stream));
-    for (int pos = 0; pos < M.b; ++pos) launch_one(M, order[pos], hp, variant, lds);
+    for (int pos = 0; pos < M.b; ++pos) launch_one(M, order[pos], hp, variant);
     BMF_HIP(hipEventRecord(ev1, M.stream));
     M.pending.emplace_back(ev0, ev1);
     M.sgd_launches += M.b;
     if (M.pending.size() > 64) harvest_timing(M, false);
 }
 
-template <int KPL, bool FULL, int NW>
+template <int F, bool VEC, int NW>
 static void launch_positions(const BatchProblem *d_probs, const BatchItem *d_items, int64_t count, int k,
                              const HP &hp, size_t lds, hipStream_t s) {
     static size_t attr_done = 0;
     if (lds > attr_done) {
-        set_max_lds(sgd_positions_kernel<KPL, FULL, NW>, lds);
+        set_max_lds(sgd_positions_kernel<F, VEC, NW>, lds);
         attr_done = lds;
     }
-    sgd_positions_kernel<KPL, FULL, NW><<<(unsigned)count, NW * WAVE, lds, s>>>(d_probs, d_items, k, hp);
+    sgd_positions_kernel<F, VEC, NW><<<(unsigned)count, NW * WAVE, lds, s>>>(d_probs, d_items, k, hp);
     BMF_HIP(hipGetLastError());
 }
 
 void sgd_positions_launch(int k, int nw, const BatchProblem *d_probs, const BatchItem *d_items, int64_t count,
                           const HP &hp, size_t lds, hipStream_t s) {
     if (count == 0) return;
-    if (!lds_kernel_ok(k, nw)) BMF_FAIL(BMF_E_INVAL, "batched training needs k <= 128 and 4 or 8 waves per block");
-    const int kpl = (k + WAVE - 1) / WAVE;
-    const bool full = k == WAVE * kpl;
-    const int key = (kpl - 1) * 4 + (full ? 2 : 0) + (nw == 8 ? 1 : 0);
-    switch (key) {
+    if (!plan_kp(k) || (nw != 4 && nw != 8))
+        BMF_FAIL(BMF_E_INVAL, "batched training needs k <= 128 and 4 or 8 waves per block");
+    switch (plan_key(k, nw)) {
     case 0: launch_positions<1, false, 4>(d_probs, d_items, count, k, hp, lds, s); break;
     case 1: launch_positions<1, false, 8>(d_probs, d_items, count, k, hp, lds, s); break;
     case 2: launch_positions<1, true, 4>(d_probs, d_items, count, k, hp, lds, s); break;
@@ -516,7 +543,15 @@ void sgd_positions_launch(int k, int nw, const BatchProblem *d_probs, const Batc
     case 4: launch_positions<2, false, 4>(d_probs, d_items, count, k, hp, lds, s); break;
     case 5: launch_positions<2, false, 8>(d_probs, d_items, count, k, hp, lds, s); break;
     case 6: launch_positions<2, true, 4>(d_probs, d_items, count, k, hp, lds, s); break;
-    default: launch_positions<2, true, 8>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 7: launch_positions<2, true, 8>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 8: launch_positions<4, false, 4>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 9: launch_positions<4, false, 8>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 10: launch_positions<4, true, 4>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 11: launch_positions<4, true, 8>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 12: launch_positions<8, false, 4>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 13: launch_positions<8, false, 8>(d_probs, d_items, count, k, hp, lds, s); break;
+    case 14: launch_positions<8, true, 4>(d_probs, d_items, count, k, hp, lds, s); break;
+    default: launch_positions<8, true, 8>(d_probs, d_items, count, k, hp, lds, s); break;
     }
 }
 

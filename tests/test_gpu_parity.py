@@ -144,7 +144,8 @@ def test_one_epoch_factors_within_1e4(B, orc, kernel):
 
 
 @pytest.mark.parametrize("k,b,m,n,nnz,dup", [(13, 3, 200, 150, 4000, True), (64, 8, 500, 300, 20000, False),
-                                             (128, 4, 300, 100, 9000, True), (100, 5, 123, 77, 3000, True)])
+                                             (128, 4, 300, 100, 9000, True), (100, 5, 123, 77, 3000, True),
+                                             (128, 2, 2000, 580, 30000, True), (32, 1, 900, 700, 25000, True)])
 def test_kernels_bit_identical_and_close_to_oracle(B, orc, k, b, m, n, nnz, dup):
     rat = synth.random_coo(m, n, nnz, seed=k * 31 + b, dup=dup)
     outs = []
@@ -160,6 +161,21 @@ def test_kernels_bit_identical_and_close_to_oracle(B, orc, k, b, m, n, nnz, dup)
     d = max(np.abs(outs[1][0] - O.P).max(), np.abs(outs[1][1] - O.Q).max())
     log("k", k, "b", b, "2 epochs max abs diff", d)
     assert d <= 1e-4
+
+
+def test_large_k_uses_reference_kernel(B, orc):
+    # k > 128: no plan; the automatic choice runs the 64-lane reference kernel
+    rat = synth.random_coo(150, 90, 3000, seed=5, dup=True)
+    G, O = make_pair(B, orc, 150, 90, 200, 3, rat, kernel=0)
+    with pytest.raises(B.BmfError) as ex:
+        G.set_option(B.OPT_SGD_KERNEL, 2)
+        G.epoch(0.01, 0.02)
+    assert ex.value.status == B.BMF_E_STATE
+    G.set_option(B.OPT_SGD_KERNEL, 0)
+    for _ in range(2):
+        G.epoch(0.01, 0.02)
+        O.epoch(0.01, 0.02)
+    assert max_abs_diff(G, O) <= 1e-4
 
 
 def test_twenty_epochs_rmse_within_1e3(B, orc):

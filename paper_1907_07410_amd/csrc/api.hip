@@ -447,12 +447,29 @@ bmf_status bmf_debug_block_plan(int64_t n, const int32_t *u_local, const int32_t
                 return BMF_E_INVAL;
             ui[x] = ((uint32_t)u_local[x] << ibits) | (uint32_t)i_local[x];
         }
-        std::vector<bmf::SlotRec> recs;
-        const int64_t st = bmf::plan_block(ui.data(), r, n, ibits, cb, slots, chunk, recs);
+        std::vector<bmf::PlanEntry> ent;
+        const int64_t st = bmf::plan_block(ui.data(), n, ibits, cb, slots, chunk, ent);
         *n_steps = st;
         if (out) {
             if (max_steps < st) return BMF_E_RANGE;
-            std::memcpy(out, recs.data(), recs.size() * sizeof(bmf::SlotRec));
+            for (size_t q = 0; q < ent.size(); ++q) {
+                uint32_t *o = out + 4 * q;
+                const int64_t x = ent[q].x;
+                if (x < 0) {
+                    o[0] = (uint32_t)cb | ((uint32_t)slots << 16);
+                    o[1] = 0u;
+                    o[2] = 0u;
+                    o[3] = 0xffffffffu;
+                    continue;
+                }
+                const bool first = x == 0 || u_local[x - 1] != u_local[x];
+                const bool last = x + 1 == n || u_local[x + 1] != u_local[x];
+                o[0] = (uint32_t)i_local[x] | ((uint32_t)ent[q].slot << 16) | (first ? 1u << 30 : 0u) |
+                       (last ? 1u << 31 : 0u);
+                std::memcpy(&o[1], &r[x], 4);
+                o[2] = (uint32_t)u_local[x];
+                o[3] = (uint32_t)x;
+            }
         }
     } catch (const bmf::Error &e) {
         g_create_error = e.msg;

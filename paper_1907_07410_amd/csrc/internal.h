@@ -39,48 +39,59 @@ struct Rec {
     float r;
 };
 
-// One rating slot of a plan step (16 bytes): meta = item_local | slot << 16
-// | FIRST | LAST (FIRST: the user's first rating in the block, its row is
-// loaded into the slot before the step's chunk; LAST: its final rating,
-// the slot is written back after the step's chunk), the rating, the user's
-// local row, and the rating's index inside the block (all ones for an
-// empty slot).
+// Plans of the LDS-staged SGD kernel (plan.hip).  The scheduler fills PLAN_W
+// positions per step with a rating index (-1 when empty) and the LDS slot of
+// its user.
+struct PlanEntry {
+    int32_t x;
+    int32_t slot;
+};
+// Device record of one position (16 bytes): LDS byte offsets (from the
+// start of the kernel's dynamic LDS) of the item row and of the user slot
+// row (each row holds kp factors, then the bias), the rating, and the
+// user's local row | FIRST | LAST.  FIRST: the user's first rating in the
+// block (its row is loaded into the slot before the step's chunk); LAST:
+// its final one (the slot is written back after the step's chunk).  Empty
+// positions point at the dummy item row and dummy slot, with ulf = 0.
 struct SlotRec {
-    uint32_t meta;
+    uint32_t qa;
     float r;
-    uint32_t ul;
-    uint32_t idx;
+    uint32_t ua;
+    uint32_t ulf;
 };
 constexpr int PLAN_W = 4;            // ratings per step (16-lane groups of one wavefront)
-constexpr int PLAN_CH = 16;          // steps per chunk
+#ifndef BMF_PLAN_CH
+#define BMF_PLAN_CH 16
+#endif
+constexpr int PLAN_CH = BMF_PLAN_CH;  // steps per chunk
 constexpr int PLAN_MAX_HELPERS = 7;  // helper wavefronts per workgroup, at most
+// The planned kernels use a static LDS buffer of this size (all of a gfx950
+// CU's LDS; a workgroup per CU), so LDS addresses fold into instructions.
+constexpr int PLAN_LDS_BYTES = 160 * 1024;
 constexpr int PLAN_MAX_SLOTS = 4095;
 constexpr int PLAN_MIN_SLOTS = 8;
-constexpr uint32_t PLAN_SLOT_MASK = 0x3fffu;
-constexpr uint32_t PLAN_FIRST = 1u << 30, PLAN_LAST = 1u << 31;
+constexpr uint32_t PLAN_FIRST = 1u << 30, PLAN_LAST = 1u << 31, PLAN_UL_MASK = (1u << 30) - 1u;
 
-// LDS layout of the planned kernel: item slice (cb + 1 rows of kp floats,
-// the last one a dummy for empty slots), item biases, three chunks of slot
-// records, per-helper compaction lists, S + 1 user slots (slot S the
-// dummy) and their biases.
+// LDS layout of the planned kernel: the item slice (cb + 1 rows, the last a
+// dummy for empty positions), three chunks of records, per-helper
+// compaction lists, and S + 1 user slots (slot S the dummy).  A row is kp
+// factors followed by the bias, padded to kp + 4 floats.
 struct PlanLds {
-    size_t q, bi, rec, scr, u, bu, total;
+    size_t q, rec, scr, u, total;
+    int row_bytes;
 };
 __host__ __device__ inline PlanLds plan_lds(int kp, int64_t cb, int S, int CH) {
     PlanLds L;
+    L.row_bytes = (kp + 4) * 4;
     size_t o = 0;
     L.q = o;
-    o += (size_t)(cb + 1) * kp * 4;
-    L.bi = o;
-    o += (size_t)((cb + 1 + 3) / 4) * 16;
+    o += (size_t)(cb + 1) * L.row_bytes;
     L.rec = o;
     o += (size_t)3 * CH * PLAN_W * sizeof(SlotRec);
     L.scr = o;
     o += (size_t)PLAN_MAX_HELPERS * 64 * 8;
     L.u = o;
-    o += (size_t)(S + 1) * kp * 4;
-    L.bu = o;
-    o += (size_t)((S + 1 + 3) / 4) * 16;
+    o += (size_t)(S + 1) * L.row_bytes;
     L.total = o;
     return L;
 }
@@ -214,8 +225,7 @@ void build_partition(Partition &out, const int32_t *u, const int32_t *i, const f
 // planned kernel does not apply).
 int plan_kp(int k);
 int plan_slots(int kp, int64_t cb, int CH, int max_lds);
-int64_t plan_block(const uint32_t *ui, const float *r, int64_t n, int ibits, int cb, int S, int CH,
-                   std::vector<SlotRec> &out);
+int64_t plan_block(const uint32_t *ui, int64_t n, int ibits, int cb, int S, int CH, std::vector<PlanEntry> &out);
 void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hipStream_t s);
 
 // SGD: run one epoch of strata in `order`.

@@ -48,8 +48,8 @@ struct Scratch {
 
 // One attempt; returns false on a stall (only possible when users start
 // out of order).
-bool schedule_block(const uint32_t *ui, const float *r, int64_t n, int ibits, int cb, int S, int CH,
-                    bool in_order, std::vector<SlotRec> &out, Scratch &z) {
+bool schedule_block(const uint32_t *ui, int64_t n, int ibits, int cb, int S, int CH, bool in_order,
+                    std::vector<PlanEntry> &out, Scratch &z) {
     const uint32_t imask = (1u << ibits) - 1u;
     const int N = (int)n;
     z.next_u.assign(N, -1);
@@ -81,7 +81,6 @@ bool schedule_block(const uint32_t *ui, const float *r, int64_t n, int ibits, in
     std::deque<std::pair<int32_t, int32_t>> free_slots;  // (slot, first chunk it may be loaded for)
     for (int q = 0; q < S; ++q) free_slots.push_back({q, 0});
     int next_new = 0;  // first rating of the lowest unstarted user
-    const SlotRec bubble{(uint32_t)cb | ((uint32_t)S << 16), 0.f, 0u, 0xffffffffu};
     out.clear();
     int done = 0;
     for (int64_t s = 0; done < N; ++s) {
@@ -103,10 +102,13 @@ bool schedule_block(const uint32_t *ui, const float *r, int64_t n, int ibits, in
             if (cc >= 0 && (cn < 0 || cc < cn)) {
                 x = cc;
                 ready_cont.pop();
-                z.slot[x] = z.slot[x - 1];
             } else if (cn >= 0) {
                 x = cn;
                 ready_new.pop();
+            } else {
+                break;
+            }
+            if (z.first[x]) {
                 z.slot[x] = free_slots.front().first;
                 free_slots.pop_front();
                 z.started[x] = 1;
@@ -116,13 +118,10 @@ bool schedule_block(const uint32_t *ui, const float *r, int64_t n, int ibits, in
                     next_new = y;
                 }
             } else {
-                break;
+                z.slot[x] = z.slot[x - 1];
             }
-            const bool last = z.next_u[x] < 0;
-            if (last) free_slots.push_back({z.slot[x], chunk + 3});
-            const uint32_t flags = (z.first[x] ? PLAN_FIRST : 0u) | (last ? PLAN_LAST : 0u);
-            out.push_back(SlotRec{(ui[x] & imask) | ((uint32_t)z.slot[x] << 16) | flags, r[x], ui[x] >> ibits,
-                                  (uint32_t)x});
+            if (z.next_u[x] < 0) free_slots.push_back({z.slot[x], chunk + 3});
+            out.push_back(PlanEntry{x, z.slot[x]});
             ++done;
             ++picked;
             for (const int y : {z.next_u[x], z.next_i[x]}) {
@@ -131,7 +130,7 @@ bool schedule_block(const uint32_t *ui, const float *r, int64_t n, int ibits, in
                 if (--z.npred[y] == 0) pend.push({z.earliest[y], y});
             }
         }
-        for (; picked < PLAN_W; ++picked) out.push_back(bubble);
+        for (; picked < PLAN_W; ++picked) out.push_back(PlanEntry{-1, S});
         // Nothing can run now and nothing ever will: every slot is held and
         // no held user has a rating in flight.
         if (done < N && pend.empty() && ready_cont.empty() && free_slots.empty()) return false;
@@ -147,19 +146,19 @@ int plan_kp(int k) {
     return 0;
 }
 
-int64_t plan_block(const uint32_t *ui, const float *r, int64_t n, int ibits, int cb, int S, int CH,
-                   std::vector<SlotRec> &out) {
+int64_t plan_block(const uint32_t *ui, int64_t n, int ibits, int cb, int S, int CH, std::vector<PlanEntry> &out) {
     if (S < 1 || CH < 1 || S > PLAN_MAX_SLOTS) BMF_FAIL(BMF_E_INVAL, "plan needs 1 to 4095 user slots and CH >= 1");
     if (n >= INT32_MAX) BMF_FAIL(BMF_E_RANGE, "block too large to plan");
     Scratch z;
-    if (!schedule_block(ui, r, n, ibits, cb, S, CH, false, out, z)) {
-        const bool ok = schedule_block(ui, r, n, ibits, cb, S, CH, true, out, z);
+    if (!schedule_block(ui, n, ibits, cb, S, CH, false, out, z)) {
+        const bool ok = schedule_block(ui, n, ibits, cb, S, CH, true, out, z);
         if (!ok) BMF_FAIL(BMF_E_STATE, "block plan stalled with users starting in order");
     }
     return (int64_t)out.size() / PLAN_W;
 }
 
 int plan_slots(int kp, int64_t cb, int CH, int max_lds) {
+    max_lds = std::min(max_lds, PLAN_LDS_BYTES);
     const PlanLds L0 = plan_lds(kp, cb, 0, CH);
     const int64_t room = (int64_t)max_lds - (int64_t)L0.total;
     if (room <= 0) return 0;
@@ -171,16 +170,19 @@ int plan_slots(int kp, int64_t cb, int CH, int max_lds) {
 void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hipStream_t s) {
     out.ok = false;
     const int kp = plan_kp(k);
-    if (!kp || part.cb + 1 > (1 << 16)) return;
+    if (!kp || part.cb + 1 > (1 << 16) || part.ubits > 30) return;
     const int CH = PLAN_CH;
     const int S = plan_slots(kp, part.cb, CH, max_lds);
     if (S < PLAN_MIN_SLOTS) return;
+    const PlanLds L = plan_lds(kp, part.cb, S, CH);
     const int64_t nblk = (int64_t)b * b;
     std::vector<Rec> recs(part.nnz);
     if (part.nnz) {
         BMF_HIP(hipMemcpyAsync(recs.data(), part.recs.p, part.nnz * sizeof(Rec), hipMemcpyDeviceToHost, s));
         BMF_HIP(hipStreamSynchronize(s));
     }
+    const uint32_t imask = (1u << part.ibits) - 1u;
+    const int ibits = part.ibits;
     std::vector<std::vector<SlotRec>> per(nblk);
     std::atomic<int64_t> next{0};
     std::atomic<bool> failed{false};
@@ -188,23 +190,37 @@ void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hip
     std::mutex fail_mu;
     auto worker = [&] {
         std::vector<uint32_t> ui;
-        std::vector<float> r;
+        std::vector<PlanEntry> ent;
         for (;;) {
             const int64_t blk = next.fetch_add(1);
             if (blk >= nblk || failed.load()) return;
             const int64_t beg = part.h_block_ptr[blk], end = part.h_block_ptr[blk + 1];
-            ui.resize(end - beg);
-            r.resize(end - beg);
-            for (int64_t x = beg; x < end; ++x) {
-                ui[x - beg] = recs[x].ui;
-                r[x - beg] = recs[x].r;
-            }
+            const int64_t cnt = end - beg;
+            ui.resize(cnt);
+            for (int64_t x = 0; x < cnt; ++x) ui[x] = recs[beg + x].ui;
             try {
-                plan_block(ui.data(), r.data(), end - beg, part.ibits, (int)part.cb, S, CH, per[blk]);
+                plan_block(ui.data(), cnt, ibits, (int)part.cb, S, CH, ent);
             } catch (const Error &e) {
                 std::lock_guard<std::mutex> g(fail_mu);
                 fail_msg = e.msg;
                 failed = true;
+                return;
+            }
+            auto &o = per[blk];
+            o.resize(ent.size());
+            for (size_t q = 0; q < ent.size(); ++q) {
+                const int x = ent[q].x;
+                if (x < 0) {
+                    o[q] = SlotRec{(uint32_t)(L.q + (size_t)part.cb * L.row_bytes), 0.f,
+                                   (uint32_t)(L.u + (size_t)S * L.row_bytes), 0u};
+                    continue;
+                }
+                const uint32_t u = ui[x] >> ibits;
+                const bool first = x == 0 || (ui[x - 1] >> ibits) != u;
+                const bool last = x + 1 == cnt || (ui[x + 1] >> ibits) != u;
+                o[q] = SlotRec{(uint32_t)(L.q + (size_t)(ui[x] & imask) * L.row_bytes), recs[beg + x].r,
+                               (uint32_t)(L.u + (size_t)ent[q].slot * L.row_bytes),
+                               u | (first ? PLAN_FIRST : 0u) | (last ? PLAN_LAST : 0u)};
             }
         }
     };

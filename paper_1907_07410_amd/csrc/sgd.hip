@@ -34,19 +34,22 @@ __device__ __forceinline__ float lane_dot(const float (&p)[KPL], const float (&q
     return d;
 }
 
-// Eqs 10-13, one residual from pre-update values, explicit FMAs so that
-// every kernel rounds identically:
-//   g = err*other - beta*self (one fma, beta*self rounded first)
-//   self' = self + alpha*g     (one fma)
+// Eqs 10 and 11 from pre-update values:
+//   self + alpha (err * other - beta * self)
+//     = fma(alpha * err, other, fma(-(alpha * beta), self, self)),
+// two FMAs per factor with the products alpha*err (per rating) and
+// alpha*beta (a constant) rounded once.  The decay self - alpha beta self is
+// one rounding of the exact value, so no rounding is repeated the same way
+// at every update.  Every kernel uses this helper and rounds identically.
 template <int KPL>
 __device__ __forceinline__ void factor_update(float (&p)[KPL], float (&q)[KPL], float e, const HP &hp) {
+    const float ape = hp.a_p * e, aqe = hp.a_q * e;
+    const float dp = -(hp.a_p * hp.b_p), dq = -(hp.a_q * hp.b_q);
 #pragma unroll
     for (int c = 0; c < KPL; ++c) {
         const float pc = p[c], qc = q[c];
-        const float gp = fmaf(e, qc, -(hp.b_p * pc));
-        const float gq = fmaf(e, pc, -(hp.b_q * qc));
-        p[c] = fmaf(hp.a_p, gp, pc);
-        q[c] = fmaf(hp.a_q, gq, qc);
+        p[c] = fmaf(ape, qc, fmaf(dp, pc, pc));
+        q[c] = fmaf(aqe, pc, fmaf(dq, qc, qc));
     }
 }
 
@@ -159,8 +162,10 @@ __global__ __launch_bounds__(64) void sgd_ref16_kernel(const Rec *__restrict__ r
 //  * every user active in the block has an LDS slot holding p_u and bu_u;
 //  * per step each group reads its slot record (item, slot, rating), its
 //    user and item rows, does the update of Eqs 10-13 with the dot product
-//    summed over its 16 lanes, and writes both rows back.  Empty slots point
-//    at a dummy user slot and a dummy item row.
+//    summed over its 16 lanes, and writes both rows back.  Records carry
+//    the rows' LDS addresses, and each row keeps its bias after the
+//    factors.  Empty positions point at a dummy user slot and a dummy item
+//    row.
 // The other wavefronts are helpers.  Steps go in chunks of CH; while
 // wavefront 0 runs chunk c the helpers write back to global memory the user
 // rows whose last rating was in chunk c-1 and stage chunk c+1: its slot
@@ -210,37 +215,33 @@ __device__ __forceinline__ void planned_block(const SlotRec *__restrict__ steps,
                                               float *Q, float *bu, float *bi, float mu, const HP &hp,
                                               unsigned char *smem) {
     constexpr int KP = 16 * F;
+    constexpr int RS = KP + 4;  // floats per LDS row: factors, bias, padding
     constexpr int WG = NW * WAVE;
     constexpr int NH = NW - 1;
     constexpr int RB = 2;  // rows in flight per 16-lane group while staging
     if (nsteps <= 0) return;
     const PlanLds L = plan_lds(KP, cb, S, CH);
     float *Qs = reinterpret_cast<float *>(smem + L.q);
-    float *Bis = reinterpret_cast<float *>(smem + L.bi);
     SlotRec *Rb = reinterpret_cast<SlotRec *>(smem + L.rec);
     uint2 *Scr = reinterpret_cast<uint2 *>(smem + L.scr);
     float *Us = reinterpret_cast<float *>(smem + L.u);
-    float *Bus = reinterpret_cast<float *>(smem + L.bu);
     const int ncols = (int)std::min<int64_t>(cb, n - i0);
     const int tid = threadIdx.x, wave = tid / WAVE, lane = tid % WAVE;
     const int g = lane >> 4, gl = lane & 15;
     const int RPC = CH * PLAN_W;
     const int nch = (int)((nsteps + CH - 1) / CH);
 
-    // item slice (zero beyond k), dummy item row and dummy user slot
+    // item slice: factors (zero beyond k) and bias per row; dummy item row
+    // and dummy user slot zeroed
     for (int64_t x = tid; x < (int64_t)ncols * KP; x += WG) {
         const int64_t il = x / KP;
         const int f = (int)(x % KP);
-        Qs[x] = f < k ? Q[(i0 + il) * k + f] : 0.f;
+        Qs[il * RS + f] = f < k ? Q[(i0 + il) * k + f] : 0.f;
     }
-    for (int x = tid; x < ncols; x += WG) Bis[x] = bi[i0 + x];
-    if (tid < KP) {
-        Qs[(size_t)cb * KP + tid] = 0.f;
-        Us[(size_t)S * KP + tid] = 0.f;
-    }
-    if (tid == 0) {
-        Bis[cb] = 0.f;
-        Bus[S] = 0.f;
+    for (int x = tid; x < ncols; x += WG) Qs[(int64_t)x * RS + KP] = bi[i0 + x];
+    if (tid < RS) {
+        Qs[(size_t)cb * RS + tid] = 0.f;
+        Us[(size_t)S * RS + tid] = 0.f;
     }
 
     const int hw = wave - 1;
@@ -255,15 +256,16 @@ __device__ __forceinline__ void planned_block(const SlotRec *__restrict__ steps,
             const bool valid = x < cnt;
             SlotRec rec{0u, 0.f, 0u, 0u};
             if (valid) rec = src[x];
-            const bool last = valid && (rec.meta & PLAN_LAST);
+            const bool last = valid && (rec.ulf & PLAN_LAST);
             const uint64_t mask = __ballot(last);
             const int nl = __popcll(mask);
-            if (last) scr[lane_rank(mask)] = make_uint2(rec.ul, (rec.meta >> 16) & PLAN_SLOT_MASK);
+            if (last) scr[lane_rank(mask)] = make_uint2(rec.ulf & PLAN_UL_MASK, rec.ua);
             for (int e = g; e < nl; e += 4) {
                 const uint2 en = scr[e];
                 const int64_t row = u0 + en.x;
+                const float *srow = reinterpret_cast<const float *>(smem + en.y);
                 float v[F];
-                row_ld<F>(v, Us + (size_t)en.y * KP + gl * F);
+                row_ld<F>(v, srow + gl * F);
                 if (VEC) {
                     row_st<F>(P + row * k + gl * F, v);
                 } else {
@@ -271,7 +273,7 @@ __device__ __forceinline__ void planned_block(const SlotRec *__restrict__ steps,
                     for (int c2 = 0; c2 < F; ++c2)
                         if (gl * F + c2 < k) P[row * k + gl * F + c2] = v[c2];
                 }
-                if (gl == 0) bu[row] = Bus[en.y];
+                if (gl == 0) bu[row] = srow[KP];
             }
         }
     };
@@ -286,25 +288,25 @@ __device__ __forceinline__ void planned_block(const SlotRec *__restrict__ steps,
             const bool valid = x < cnt;
             SlotRec rec{0u, 0.f, 0u, 0u};
             if (valid) rec = src[x];
-            const bool first = valid && (rec.meta & PLAN_FIRST);
+            const bool first = valid && (rec.ulf & PLAN_FIRST);
             if (valid) dst[x] = rec;
             const uint64_t mask = __ballot(first);
             const int nf = __popcll(mask);
-            if (first) scr[lane_rank(mask)] = make_uint2(rec.ul, (rec.meta >> 16) & PLAN_SLOT_MASK);
+            if (first) scr[lane_rank(mask)] = make_uint2(rec.ulf & PLAN_UL_MASK, rec.ua);
             for (int e0 = 0; e0 < nf; e0 += 4 * RB) {
                 float v[RB][F];
                 float bv[RB];
-                uint32_t sl[RB];
+                uint32_t ua[RB];
 #pragma unroll
                 for (int jj = 0; jj < RB; ++jj) {
                     const int e = e0 + 4 * jj + g;
-                    sl[jj] = 0xffffffffu;
+                    ua[jj] = 0xffffffffu;
                     bv[jj] = 0.f;
 #pragma unroll
                     for (int c2 = 0; c2 < F; ++c2) v[jj][c2] = 0.f;
                     if (e < nf) {
                         const uint2 en = scr[e];
-                        sl[jj] = en.y;
+                        ua[jj] = en.y;
                         const int64_t row = u0 + en.x;
                         if (VEC) {
                             row_ld<F>(v[jj], P + row * k + gl * F);
@@ -318,9 +320,10 @@ __device__ __forceinline__ void planned_block(const SlotRec *__restrict__ steps,
                 }
 #pragma unroll
                 for (int jj = 0; jj < RB; ++jj) {
-                    if (sl[jj] != 0xffffffffu) {
-                        row_st<F>(Us + (size_t)sl[jj] * KP + gl * F, v[jj]);
-                        Bus[sl[jj]] = bv[jj];
+                    if (ua[jj] != 0xffffffffu) {
+                        float *drow = reinterpret_cast<float *>(smem + ua[jj]);
+                        row_st<F>(drow + gl * F, v[jj]);
+                        drow[KP] = bv[jj];
                     }
                 }
             }
@@ -333,27 +336,34 @@ __device__ __forceinline__ void planned_block(const SlotRec *__restrict__ steps,
         if (wave == 0) {
             const SlotRec *rb = Rb + (size_t)(c % 3) * RPC;
             const int len = (int)std::min<int64_t>(CH, nsteps - (int64_t)c * CH);
-            uint2 nx = *reinterpret_cast<const uint2 *>(&rb[g]);
-            for (int t = 0; t < len; ++t) {
-                const uint32_t meta = nx.x;
-                const float r = __uint_as_float(nx.y);
-                const int tn = t + 1 < len ? t + 1 : t;
-                nx = *reinterpret_cast<const uint2 *>(&rb[tn * PLAN_W + g]);
-                const uint32_t il = meta & 0xffffu, us = (meta >> 16) & PLAN_SLOT_MASK;
-                float *pr = Us + (size_t)us * KP + gl * F;
-                float *qr = Qs + (size_t)il * KP + gl * F;
+            // One step: the group's user and item rows (and biases) from
+            // LDS, the update, the rows back to LDS.  Steps go in pairs so
+            // that the registers a step writes back from are not the ones
+            // the next step loads into (a load into a register that a
+            // pending LDS write still reads would wait for that write).
+            auto step = [&](const uint4 rec) {
+                float *urow = reinterpret_cast<float *>(smem + rec.z);
+                float *qrow = reinterpret_cast<float *>(smem + rec.x);
+                const float bu0 = urow[KP], bi0 = qrow[KP];
                 float p[F], q[F];
-                row_ld<F>(p, pr);
-                row_ld<F>(q, qr);
-                const float bu0 = Bus[us], bi0 = Bis[il];
+                row_ld<F>(p, urow + gl * F);
+                row_ld<F>(q, qrow + gl * F);
                 const float dot = row16_sum(lane_dot(p, q));
-                const float e = residual(r, mu, bu0, bi0, dot);
+                const float e = residual(__uint_as_float(rec.y), mu, bu0, bi0, dot);
                 factor_update(p, q, e, hp);
-                row_st<F>(pr, p);
-                row_st<F>(qr, q);
-                Bus[us] = bias_update(bu0, e, hp.a_bu, hp.b_bu);
-                Bis[il] = bias_update(bi0, e, hp.a_bi, hp.b_bi);
+                row_st<F>(urow + gl * F, p);
+                row_st<F>(qrow + gl * F, q);
+                urow[KP] = bias_update(bu0, e, hp.a_bu, hp.b_bu);
+                qrow[KP] = bias_update(bi0, e, hp.a_bi, hp.b_bi);
+            };
+            int t = 0;
+            for (; t + 1 < len; t += 2) {
+                const uint4 r0 = *reinterpret_cast<const uint4 *>(&rb[t * PLAN_W + g]);
+                const uint4 r1 = *reinterpret_cast<const uint4 *>(&rb[(t + 1) * PLAN_W + g]);
+                step(r0);
+                step(r1);
             }
+            if (t < len) step(*reinterpret_cast<const uint4 *>(&rb[t * PLAN_W + g]));
         } else {
             if (c > 0) write_back(c - 1);
             if (c + 1 < nch) stage(c + 1);
@@ -365,9 +375,9 @@ __device__ __forceinline__ void planned_block(const SlotRec *__restrict__ steps,
     for (int64_t x = tid; x < (int64_t)ncols * KP; x += WG) {
         const int64_t il = x / KP;
         const int f = (int)(x % KP);
-        if (f < k) Q[(i0 + il) * k + f] = Qs[x];
+        if (f < k) Q[(i0 + il) * k + f] = Qs[il * RS + f];
     }
-    for (int x = tid; x < ncols; x += WG) bi[i0 + x] = Bis[x];
+    for (int x = tid; x < ncols; x += WG) bi[i0 + x] = Qs[(int64_t)x * RS + KP];
 }
 
 // One stratum s: workgroup j owns block ((j + s) mod b, j).
@@ -377,7 +387,7 @@ __global__ __launch_bounds__(NW *WAVE) void sgd_plan_kernel(const SlotRec *__res
                                                             int64_t n, int64_t rb, int64_t cb, int k, int S, int CH,
                                                             float *P, float *Q, float *bu, float *bi, float mu,
                                                             HP hp) {
-    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ __align__(16) unsigned char smem[PLAN_LDS_BYTES];
     const int j = blockIdx.x;
     const int br = (j + s) % b;
     const int64_t blk = (int64_t)br * b + j;
@@ -398,7 +408,7 @@ template <int F, bool VEC, int NW>
 __global__ __launch_bounds__(NW *WAVE) void sgd_positions_kernel(const BatchProblem *__restrict__ probs,
                                                                  const BatchItem *__restrict__ items, int k,
                                                                  HP hp) {
-    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ __align__(16) unsigned char smem[PLAN_LDS_BYTES];
     const BatchItem it = items[blockIdx.x];
     const BatchProblem pr = probs[it.p];
     const int r = (it.j + it.s) % pr.b;
@@ -429,20 +439,9 @@ static void launch_ref16(Model &M, int s, const HP &hp) {
     BMF_HIP(hipGetLastError());
 }
 
-template <class K>
-static void set_max_lds(K *fn, size_t bytes) {
-    BMF_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-}
-
 template <int F, bool VEC, int NW>
 static void launch_plan(Model &M, int s, const HP &hp) {
-    const size_t lds = plan_lds(16 * F, M.part.cb, M.plan.S, M.plan.CH).total;
-    static size_t attr_done = 0;  // per instantiation
-    if (lds > attr_done) {
-        set_max_lds(sgd_plan_kernel<F, VEC, NW>, lds);
-        attr_done = lds;
-    }
-    sgd_plan_kernel<F, VEC, NW><<<M.b, NW * WAVE, lds, M.stream>>>(
+    sgd_plan_kernel<F, VEC, NW><<<M.b, NW * WAVE, 0, M.stream>>>(
         M.plan.steps.as<SlotRec>(), M.plan.blk_step.as<int64_t>(), M.b, s, M.n, M.part.rb, M.part.cb, M.k,
         M.plan.S, M.plan.CH, M.P.as<float>(), M.Q.as<float>(), M.bu.as<float>(), M.bi.as<float>(), (float)M.mu, hp);
     BMF_HIP(hipGetLastError());
@@ -521,12 +520,8 @@ void sgd_epoch(Model &M, const int32_t *order, const HP &hp) {
 template <int F, bool VEC, int NW>
 static void launch_positions(const BatchProblem *d_probs, const BatchItem *d_items, int64_t count, int k,
                              const HP &hp, size_t lds, hipStream_t s) {
-    static size_t attr_done = 0;
-    if (lds > attr_done) {
-        set_max_lds(sgd_positions_kernel<F, VEC, NW>, lds);
-        attr_done = lds;
-    }
-    sgd_positions_kernel<F, VEC, NW><<<(unsigned)count, NW * WAVE, lds, s>>>(d_probs, d_items, k, hp);
+    if (lds > (size_t)PLAN_LDS_BYTES) BMF_FAIL(BMF_E_STATE, "plan exceeds the LDS kernel's buffer");
+    sgd_positions_kernel<F, VEC, NW><<<(unsigned)count, NW * WAVE, 0, s>>>(d_probs, d_items, k, hp);
     BMF_HIP(hipGetLastError());
 }
 

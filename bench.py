@@ -27,9 +27,29 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch of the SGD stratum kernel on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors
+# that make the counters match a plain 256 MiB copy kernel), valid for the
+# kernel sources with this sha1; reported as null once they change.
+SGD_TRAFFIC = {"sources_sha1": "910e8a9631e0a3ed8d4395ba1b2509595e85d209",
+               "fetch_bytes": 26908742.6, "write_bytes": 21915840.8}
+SGD_SOURCES = ["paper_1907_07410_amd/csrc/sgd.hip", "paper_1907_07410_amd/csrc/plan.hip",
+               "paper_1907_07410_amd/csrc/internal.h", "paper_1907_07410_amd/csrc/wave.h"]
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def measured_traffic():
+    import hashlib
+    h = hashlib.sha1()
+    for f in SGD_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != SGD_TRAFFIC["sources_sha1"]:
+        return None
+    return SGD_TRAFFIC["fetch_bytes"] + SGD_TRAFFIC["write_bytes"]
 
 
 def algorithmic_bytes(u, i, m, n, b, k):
@@ -55,6 +75,53 @@ def critical_path(u, i, m, n, b, order_mode=0):
     return int(tot), int(cnt.max()), float(cnt.mean())
 
 
+def serving_leg(binding, args):
+    """Top-100 serving on the 1M-user x 100k-item, k=128 factor tables:
+    the continuous-batching server scoring in BF16 (FP32 rescoring) against
+    an FP32 server that runs one request at a time.  Each runs the same
+    request stream submitted at once (saturated throughput), then a Poisson
+    stream at half of its own saturated rate (latency at load)."""
+    from paper_1907_07410_amd import configs, serving, synth
+    sc = configs.SERVING
+    t0 = time.time()
+    P, Q, bu, bi, mu = synth.serving_factors(sc.m, sc.n, sc.k, seed=args.seed + 3)
+    G = binding.Model(sc.m, sc.n, sc.k, 1)
+    G.set_factors(P, Q, bu, bi, mu)
+    del P, bu
+    log(f"serving tables {sc.m} x {sc.n} x {sc.k} ready in {time.time() - t0:.1f}s")
+    rng = np.random.default_rng(args.seed + 11)
+    n = args.serving_requests
+    reqs = serving.make_stream(rng, n, 0, sc.m, sc.n, Q, bi, mu, topk_frac=sc.topk_frac,
+                               batch_range=sc.batch_range, foldin_range=sc.foldin_range)
+    warm = serving.make_stream(rng, 8, 0, sc.m, sc.n, Q, bi, mu, topk_frac=sc.topk_frac,
+                               batch_range=sc.batch_range, foldin_range=sc.foldin_range)
+    out = {"tables": f"{sc.m} x {sc.n}, k={sc.k}", "K": sc.K, "requests": n,
+           "mix": f"{int(sc.topk_frac * 100)}% top-{sc.K} for log-uniform {sc.batch_range} users, "
+                  f"rest fold-in of log-uniform {sc.foldin_range} ratings"}
+    users = sum(len(r.users) for r in reqs if r.kind == "topk")
+    for name, kw, prec in (("bf16_continuous_batching", dict(max_batches=2), 1),
+                           ("fp32_one_request_per_batch", dict(max_batches=1, max_requests_per_batch=1), 0)):
+        S = binding.Server(G, mem_budget_bytes=4 << 30, foldin_passes=sc.foldin_passes, foldin_lr=sc.lr,
+                           foldin_reg=sc.reg, **kw)
+        serving.run(S, warm, K=sc.K, precision=prec)
+        st = serving.run(S, reqs, K=sc.K, precision=prec)
+        sat = st["req_per_s"]
+        prng = np.random.default_rng(args.seed + 12)
+        preqs = serving.make_stream(prng, n, 0.5 * sat, sc.m, sc.n, Q, bi, mu, topk_frac=sc.topk_frac,
+                                    batch_range=sc.batch_range, foldin_range=sc.foldin_range)
+        st2 = serving.run(S, preqs, K=sc.K, precision=prec)
+        out[name] = {"saturated_req_per_s": sat, "saturated_users_per_s": users / st["elapsed_s"],
+                     "saturated_p50_ms": st["p50_ms"], "saturated_p99_ms": st["p99_ms"],
+                     "batches": st["batches"], "poisson_offered_req_per_s": 0.5 * sat,
+                     "poisson_achieved_req_per_s": st2["req_per_s"], "poisson_p50_ms": st2["p50_ms"],
+                     "poisson_p99_ms": st2["p99_ms"]}
+        log(f"serving {name}: {sat:.1f} req/s saturated (p99 {st['p99_ms']:.1f} ms); Poisson at half: "
+            f"p50 {st2['p50_ms']:.2f} ms p99 {st2['p99_ms']:.2f} ms")
+        S.close()
+    del G
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,6 +131,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--topk-users", type=int, default=4096)
     ap.add_argument("--sgd-kernel", type=int, default=0)
+    ap.add_argument("--serving-requests", type=int, default=200,
+                    help="requests per serving measurement (0 skips the serving leg)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (sharding is described in "
@@ -154,6 +225,18 @@ def main():
         topk["users"] = len(users)
         topk["items"] = prob.n
 
+    del G
+    serving_out = serving_leg(binding, args) if args.serving_requests > 0 else None
+    if args.copy_calibration_mib > 0:
+        nbytes = args.copy_calibration_mib << 20
+        x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 x (read {nbytes} B, write {nbytes} B) elementwise kernel")
+        del x, y
+
     line = {
         "metric": "rating updates/s at matched RMSE; top-100 req/s + p99 latency (BF16 vs FP32)",
         "value": value,
@@ -171,7 +254,8 @@ def main():
                                "k=64, 64x64 blocks, lr 0.005, reg 0.05",
                    "m": prob.m, "n": prob.n, "n_train": len(tr), "k": cfg.k, "b": cfg.b},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
                      "kernel": "sgd stratum kernel", "algorithmic_bytes_per_launch": abytes / cfg.b,
                      "avg_launch_ms": per_launch_ms},
         "cpu_baseline": cpu,
@@ -180,6 +264,7 @@ def main():
         "critical_path_ratings_per_epoch": cp,
         "load_s": load_s,
         "topk": topk,
+        "serving": serving_out,
     }
     print(json.dumps(line), flush=True)
 

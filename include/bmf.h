@@ -82,7 +82,7 @@ typedef enum {
      * least 8 user slots (BMF_E_STATE otherwise). */
     BMF_OPT_SGD_KERNEL = 5,
     /* waves per workgroup of the LDS-staged SGD kernel: 4 or 8 (one wave
-     * runs the update steps, the others stage data); default 4.  On a
+     * runs the update steps, the others stage data); default 8.  On a
      * batch, 0 lets the autotuner choose.  Does not change results. */
     BMF_OPT_WAVES_PER_BLOCK = 6
 } bmf_option;

@@ -165,7 +165,7 @@ struct Model {
     int64_t m = 0, n = 0;
     int k = 0, b = 0;
     uint64_t seed = 1001, order_seed = 2001;
-    int order_mode = 0, mu_mode = 0, sgd_kernel = 0, waves = 4;
+    int order_mode = 0, mu_mode = 0, sgd_kernel = 0, waves = 8;
     DevBuf P, Q, bu, bi;
     double mu = 0.0;
     // training data

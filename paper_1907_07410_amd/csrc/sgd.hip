@@ -337,10 +337,10 @@ __device__ __forceinline__ void planned_block(const SlotRec *__restrict__ steps,
             const SlotRec *rb = Rb + (size_t)(c % 3) * RPC;
             const int len = (int)std::min<int64_t>(CH, nsteps - (int64_t)c * CH);
             // One step: the group's user and item rows (and biases) from
-            // LDS, the update, the rows back to LDS.  Steps go in pairs so
-            // that the registers a step writes back from are not the ones
-            // the next step loads into (a load into a register that a
-            // pending LDS write still reads would wait for that write).
+            // LDS, the update, the rows back to LDS.  Steps go in groups of
+            // four (then two, one): fewer loop instructions, and the
+            // registers a step writes back from are not the ones the next
+            // step loads into, so its loads need not wait for those writes.
             auto step = [&](const uint4 rec) {
                 float *urow = reinterpret_cast<float *>(smem + rec.z);
                 float *qrow = reinterpret_cast<float *>(smem + rec.x);
@@ -357,6 +357,16 @@ __device__ __forceinline__ void planned_block(const SlotRec *__restrict__ steps,
                 qrow[KP] = bias_update(bi0, e, hp.a_bi, hp.b_bi);
             };
             int t = 0;
+            for (; t + 3 < len; t += 4) {
+                const uint4 r0 = *reinterpret_cast<const uint4 *>(&rb[t * PLAN_W + g]);
+                const uint4 r1 = *reinterpret_cast<const uint4 *>(&rb[(t + 1) * PLAN_W + g]);
+                const uint4 r2 = *reinterpret_cast<const uint4 *>(&rb[(t + 2) * PLAN_W + g]);
+                const uint4 r3 = *reinterpret_cast<const uint4 *>(&rb[(t + 3) * PLAN_W + g]);
+                step(r0);
+                step(r1);
+                step(r2);
+                step(r3);
+            }
             for (; t + 1 < len; t += 2) {
                 const uint4 r0 = *reinterpret_cast<const uint4 *>(&rb[t * PLAN_W + g]);
                 const uint4 r1 = *reinterpret_cast<const uint4 *>(&rb[(t + 1) * PLAN_W + g]);

@@ -122,6 +122,52 @@ def serving_leg(binding, args):
     return out
 
 
+def batched_leg(binding, args, torch):
+    """64 independent problems of uneven size (users U[10k, 200k], items
+    U[2k, 50k], density 0.1-1%, Zipf(1.1) degrees, k=32) scaled linearly in
+    users and items by --batched-scale, trained together with autotuned block
+    grids; 10 timed epochs after one warm-up epoch.  Also times one epoch of
+    every problem run alone (one after another) for comparison."""
+    from paper_1907_07410_amd import configs
+    bc = configs.BATCHED
+    t0 = time.time()
+    probs = bc.generate(args.seed, args.batched_scale)
+    nnz = [len(p.train) for p in probs]
+    log(f"batched: {len(probs)} problems, {sum(nnz)} ratings generated in {time.time() - t0:.1f}s")
+    bt = binding.Batch([(p.m, p.n) for p in probs], bc.k, seed=args.seed + 1000)
+    for q, p in enumerate(probs):
+        bt.load(q, p.train.u, p.train.i, p.train.r)
+    t0 = time.time()
+    bt.tune()
+    tune_s = time.time() - t0
+    grids = [bt.info(q)[0] for q in range(len(probs))]
+    waves = bt.info(0)[1]
+    bt.epochs(1, bc.lr, bc.reg)
+    bt.timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.epochs(bc.epochs, bc.lr, bc.reg)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, launches = bt.timing(reset=True)
+    alone_ms = 0.0
+    for q in range(len(probs)):
+        G = bt.problem(q)
+        G.sgd_timing(reset=True)
+        G.epoch(bc.lr, bc.reg)
+        G.synchronize()
+        alone_ms += G.sgd_timing(reset=True)[0]
+    out = {"problems": len(probs), "scale": args.batched_scale, "ratings": int(sum(nnz)), "k": bc.k,
+           "epochs": bc.epochs, "updates_per_s": sum(nnz) * bc.epochs / el, "epoch_ms": el * 1e3 / bc.epochs,
+           "kernel_ms_per_epoch": ms / bc.epochs, "launches_per_epoch": launches / bc.epochs,
+           "alone_sequential_epoch_ms": alone_ms, "speedup_vs_alone": alone_ms / (ms / bc.epochs),
+           "tune_s": tune_s, "waves": waves, "grids": {str(b): grids.count(b) for b in sorted(set(grids))}}
+    log(f"batched: {out['updates_per_s'] / 1e6:.0f}M updates/s, epoch {out['epoch_ms']:.2f} ms "
+        f"(alone one after another {alone_ms:.2f} ms), grids {out['grids']}, waves {waves}, tune {tune_s:.1f}s")
+    bt.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -133,6 +179,8 @@ def main():
     ap.add_argument("--sgd-kernel", type=int, default=0)
     ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests per serving measurement (0 skips the serving leg)")
+    ap.add_argument("--batched-scale", type=float, default=0.25,
+                    help="linear scale of the 64-problem batched workload's m and n (0 skips the batched leg)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -227,6 +275,7 @@ def main():
 
     del G
     serving_out = serving_leg(binding, args) if args.serving_requests > 0 else None
+    batched_out = batched_leg(binding, args, torch) if args.batched_scale > 0 else None
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
         x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -265,6 +314,7 @@ def main():
         "load_s": load_s,
         "topk": topk,
         "serving": serving_out,
+        "batched": batched_out,
     }
     print(json.dumps(line), flush=True)
 

@@ -208,7 +208,7 @@ bmf_status bmf_topk(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int
  * to pick Kc >= K candidates per user, then an FP32 rescore of those
  * candidates (fixed-order FP32 dot products) and a final exact top-K of the
  * rescored values.  The BF16 copies (round to nearest even) are made once
- * after the factors last changed.  Kc = 0 selects 2K. */
+ * after the factors last changed.  Kc = 0 selects K + max(16, K / 2). */
 bmf_status bmf_topk_bf16(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t Kc,
                          int32_t *items_out, float *scores_out);
 
@@ -303,7 +303,7 @@ typedef struct {
     int32_t max_requests_per_batch; /* 0: unlimited; 1 turns batching off */
     int32_t foldin_passes;          /* passes of a fold-in (0: 10) */
     float foldin_lr, foldin_reg;    /* fold-in step and regulariser (0: 0.005, 0.05) */
-    int32_t Kc;                     /* BF16 candidates per user (0: 2K) */
+    int32_t Kc;                     /* BF16 candidates per user (0: K + max(16, K/2)) */
 } bmf_server_config;
 
 typedef struct {

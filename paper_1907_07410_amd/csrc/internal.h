@@ -253,6 +253,9 @@ struct TopkPlan {
     size_t off_ug = 0, off_ugb = 0, off_ub = 0, off_part = 0, off_sel = 0, total = 0;
 };
 TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc);
+// BF16 candidates per user for a top-K request: Kc when given (at least K),
+// else K + max(16, K / 2).
+inline int topk_candidates(int K, int Kc) { return Kc > 0 ? (Kc > K ? Kc : K) : K + (K / 2 > 16 ? K / 2 : 16); }
 void topk_gather(Model &M, const TopkPlan &T, const int32_t *d_users, unsigned char *work, hipStream_t s);
 void topk_score(Model &M, const TopkPlan &T, unsigned char *work, int32_t *d_items, float *d_scores, hipStream_t s);
 void topk_run(Model &M, const int32_t *d_users, int64_t nu, int K, int precision, int Kc,

@@ -413,7 +413,7 @@ bmf_status submit(bmf_server *S, std::shared_ptr<Request> r, int64_t *id) {
         if (r->K < 1 || r->K > 512) BMF_FAIL(BMF_E_INVAL, "K must be in [1, 512]");
         if (r->precision != 0 && r->precision != 1) BMF_FAIL(BMF_E_INVAL, "precision must be 0 or 1");
         if (r->precision == 1) {
-            const int kc = S->cfg.Kc > 0 ? std::max(S->cfg.Kc, r->K) : 2 * r->K;
+            const int kc = topk_candidates(r->K, S->cfg.Kc);
             if (kc > 1008) BMF_FAIL(BMF_E_INVAL, "BF16 candidates per user must be at most 1008");
         }
         for (int32_t u : r->users)

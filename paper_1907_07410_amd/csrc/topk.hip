@@ -373,9 +373,7 @@ TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
     T.nu = nu;
     T.K = K;
     T.bf = precision == 1;
-    if (T.bf && Kc == 0) Kc = 2 * K;
-    if (T.bf && Kc < K) Kc = K;
-    T.Ksel = T.bf ? Kc : K;
+    T.Ksel = T.bf ? topk_candidates(K, Kc) : K;
     T.kp = round_up(M.k, 16);
     T.kb = round_up(M.k, 32);
     T.nu_pad = (nu + TU - 1) / TU * TU;

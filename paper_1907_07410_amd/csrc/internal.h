@@ -242,15 +242,23 @@ void sgd_positions_launch(int k, int nw, const BatchProblem *d_probs, const Batc
 double sq_residual_sum(const Model &M, const int32_t *u, const int32_t *i, const float *r, int64_t cnt,
                        const HP *loss_hp, DevBuf &scratch);
 
-// Top-K.  A plan fixes the split of the item range and the workspace
-// layout (user vectors FP32/BF16, per-user offsets mu + bu, candidate
-// lists); gather fills the user vectors from P, score runs selection,
-// merge, rescore and decode.  topk_run does all three on M.stream.
+// Top-K.  A plan fixes the threshold sample, the split of the item range
+// and the workspace layout (user vectors FP32/BF16, per-user offsets
+// mu + bu, thresholds, candidate buffers and lists); gather fills the user
+// vectors from P, score runs threshold, filter, finish, the full-selection
+// pass for users that need it, rescore and decode.  topk_run does both on
+// M.stream.
 struct TopkPlan {
-    int64_t nu = 0, nu_pad = 0, per_split = 0;
-    int K = 0, Ksel = 0, kp = 0, kb = 0, S = 1;
+    int64_t nu = 0, nu_pad = 0;
+    int K = 0, Ksel = 0, kp = 0, kb = 0;
     bool bf = false;
-    size_t off_ug = 0, off_ugb = 0, off_ub = 0, off_part = 0, off_sel = 0, total = 0;
+    // threshold sample: s items, threshold = the r-th best sampled score
+    // (r = 0: no threshold); candidate buffers of capg keys per user;
+    // the filter splits the item range into S pieces of per_split items
+    int s = 0, r = 0, capg = 0, S = 1;
+    int64_t per_split = 0;
+    size_t off_ug = 0, off_ugb = 0, off_ub = 0, off_thr = 0, off_cnt = 0, off_fail = 0, off_cand = 0, off_sel = 0,
+           total = 0;
 };
 TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc);
 // BF16 candidates per user for a top-K request: Kc when given (at least K),

@@ -3,10 +3,23 @@
 // global mean), ties to the smaller item id.
 //
 // The score matrix users x items is the one dense contraction of the
-// method, so it runs on MFMA and is never stored: each wave multiplies 16
-// users against 16-item tiles and filters every score against the user's
-// running K-th best, appending survivors to an LDS candidate buffer that is
-// compacted (sorted, cut to K) when it fills.
+// method, so it runs on MFMA and is never stored; the work that remains is
+// selection.  Three passes per request:
+//  1. threshold: each user's scores against a fixed sample of s = 1024
+//     evenly spaced item ids give a score that at least r sampled scores
+//     reach (a 256-bin histogram between the sample's extremes), r chosen so
+//     that the chance that fewer than the needed number of items reach it is
+//     below 1e-6 (no threshold when n <= 1024: every item is a candidate);
+//  2. filter: the full user x item contraction, split over the item range
+//     across workgroups; every score at or above the user's threshold is
+//     appended to the user's candidate buffer in global memory;
+//  3. finish: one workgroup per user sorts its candidates and keeps the best.
+// A user whose buffer got fewer than the needed candidates (or overflowed)
+// is redone by the full-selection kernel (scores filtered against a running
+// K-th best in an LDS buffer over all items), launched every time and
+// exiting at once when no user of its tile needs it.  The result is exact in
+// both cases: the best items of the candidates are the best items overall
+// whenever enough items reach the threshold.
 //
 //   FP32 path: v_mfma_f32_16x16x4_f32 on the FP32 factors.
 //   BF16 path: v_mfma_f32_16x16x32_bf16 on round-to-nearest-even BF16
@@ -14,8 +27,9 @@
 //              rescored with FP32 factors and cut to K.
 //
 // The latent index order inside an MFMA tile is fixed and independent of
-// the users sharing the tile, so a user's scores (and hence its result) do
-// not depend on the rest of the batch.
+// the users sharing the tile, and a user's threshold and candidates depend
+// on its own scores only, so a user's result does not depend on the rest of
+// the batch.
 #include <algorithm>
 #include <cmath>
 
@@ -113,78 +127,264 @@ __device__ __forceinline__ void wave_sort_desc(uint64_t *buf, int size) {
     }
 }
 
-template <int KC, int CAP, bool BF16>
-__global__ __launch_bounds__(64) void score_select_kernel(const float *__restrict__ Ug, const uint16_t *__restrict__ Ugb,
-                                                          const float *__restrict__ Qf,
-                                                          const uint16_t *__restrict__ Qb,
-                                                          const float *__restrict__ bi, int64_t n, int k, int kp,
-                                                          int kb, int K, int64_t per_split, int S,
-                                                          uint64_t *__restrict__ out) {
-    __shared__ SelShared<CAP> sh;
-    const int lane = threadIdx.x;
-    const int64_t tile = blockIdx.x;
-    const int split = blockIdx.y;
-    const int64_t ibeg = (int64_t)split * per_split;
-    const int64_t iend = std::min<int64_t>(n, ibeg + per_split);
-    const int ucol = lane % 16, grp = lane / 16;
-    const int64_t urow = tile * TU + ucol;
-
-    if (lane < TU) sh.cnt[lane] = 0;
-    float thr = -INFINITY;  // threshold of user ucol
-
-    // user operand fragments in registers
-    f32x4 bf[BF16 ? 1 : KC];
-    bf16x8 bb[BF16 ? KC : 1];
-    if (!BF16) {
-#pragma unroll
-        for (int c = 0; c < KC; ++c) {
-            bf[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-            if (c * 16 < kp) bf[c] = *reinterpret_cast<const f32x4 *>(Ug + urow * kp + c * 16 + 4 * grp);
-        }
-    } else {
-#pragma unroll
-        for (int c = 0; c < KC; ++c) {
-            uint4 raw = {0u, 0u, 0u, 0u};
-            if (c * 32 < kb) raw = *reinterpret_cast<const uint4 *>(Ugb + urow * kb + c * 32 + 8 * grp);
-            bb[c] = __builtin_bit_cast(bf16x8, raw);
-        }
-    }
-
-    for (int64_t ib = ibeg; ib < iend; ib += TI) {
-        const int64_t irow = ib + ucol;  // item row this lane feeds into the A operand
-        const bool irow_ok = irow < iend;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+// User operand fragments of a 16-user tile (rows of Ug / Ugb).
+template <int KC, bool BF16>
+struct UserFrag {
+    f32x4 f[BF16 ? 1 : KC];
+    bf16x8 b[BF16 ? KC : 1];
+    __device__ __forceinline__ void load(const float *Ug, const uint16_t *Ugb, int64_t urow, int kp, int kb, int grp) {
         if (!BF16) {
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
-                f32x4 a = {0.f, 0.f, 0.f, 0.f};
-                const int f0 = c * 16 + 4 * grp;
-                if (irow_ok) {
-                    if (f0 + 3 < k && (k & 3) == 0) {
-                        a = *reinterpret_cast<const f32x4 *>(Qf + irow * k + f0);
-                    } else {
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) a[e] = (f0 + e < k) ? Qf[irow * k + f0 + e] : 0.f;
-                    }
-                }
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], bf[c][0], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], bf[c][1], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], bf[c][2], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], bf[c][3], acc, 0, 0, 0);
+                f[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                if (c * 16 < kp) f[c] = *reinterpret_cast<const f32x4 *>(Ug + urow * kp + c * 16 + 4 * grp);
             }
         } else {
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 uint4 raw = {0u, 0u, 0u, 0u};
-                if (irow_ok && c * 32 < kb) raw = *reinterpret_cast<const uint4 *>(Qb + irow * kb + c * 32 + 8 * grp);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, raw), bb[c], acc, 0, 0, 0);
+                if (c * 32 < kb) raw = *reinterpret_cast<const uint4 *>(Ugb + urow * kb + c * 32 + 8 * grp);
+                b[c] = __builtin_bit_cast(bf16x8, raw);
             }
         }
+    }
+};
+
+// Dot products of a 16-item x 16-user tile: this lane feeds item row `irow`
+// (when irow_ok) into the A operand and receives, in acc[r], the score of
+// user (lane % 16) with item (tile item 4 * (lane / 16) + r).
+template <int KC, bool BF16>
+__device__ __forceinline__ f32x4 tile_dots(const UserFrag<KC, BF16> &U, const float *__restrict__ Qf,
+                                           const uint16_t *__restrict__ Qb, int64_t irow, bool irow_ok, int k,
+                                           int kb, int grp) {
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    if (!BF16) {
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+            f32x4 a = {0.f, 0.f, 0.f, 0.f};
+            const int f0 = c * 16 + 4 * grp;
+            if (irow_ok) {
+                if (f0 + 3 < k && (k & 3) == 0) {
+                    a = *reinterpret_cast<const f32x4 *>(Qf + irow * k + f0);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) a[e] = (f0 + e < k) ? Qf[irow * k + f0 + e] : 0.f;
+                }
+            }
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], U.f[c][0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], U.f[c][1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], U.f[c][2], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], U.f[c][3], acc, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+            uint4 raw = {0u, 0u, 0u, 0u};
+            if (irow_ok && c * 32 < kb) raw = *reinterpret_cast<const uint4 *>(Qb + irow * kb + c * 32 + 8 * grp);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, raw), U.b[c], acc, 0, 0, 0);
+        }
+    }
+    return acc;
+}
+
+constexpr int SAMPLE_MAX = 1024;
+constexpr int HBINS = 256;
+
+// Pass 1: threshold per user from its scores over the sample items
+// t * n / s, t < s: a first pass finds the sample's minimum and maximum, a
+// second counts the scores in 256 equal bins between them, and the
+// threshold is the lower edge of the bin below the one holding the r-th best
+// sampled score (so at least r sampled scores reach it, whatever the
+// rounding of the bin index).  Stored as an ordered key; 0 = no threshold
+// (r = 0).  Also clears the user's candidate count.  One wave per 16-user
+// tile; lane (u, g) handles user u and a quarter of each sample tile.
+template <int KC, bool BF16>
+__global__ __launch_bounds__(64) void sample_threshold_kernel(const float *__restrict__ Ug,
+                                                              const uint16_t *__restrict__ Ugb,
+                                                              const float *__restrict__ Qf,
+                                                              const uint16_t *__restrict__ Qb,
+                                                              const float *__restrict__ bi, int64_t n, int k, int kp,
+                                                              int kb, int s, int r, uint32_t *__restrict__ thr,
+                                                              uint32_t *__restrict__ cnt) {
+    __shared__ uint32_t hist[TU][HBINS];
+    const int lane = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int ucol = lane % 16, grp = lane / 16;
+    if (lane < TU) cnt[tile * TU + lane] = 0u;
+    if (r == 0) {
+        if (lane < TU) thr[tile * TU + lane] = 0u;
+        return;
+    }
+    for (int x = lane; x < TU * HBINS; x += WAVE) (&hist[0][0])[x] = 0u;
+    UserFrag<KC, BF16> U;
+    U.load(Ug, Ugb, tile * TU + ucol, kp, kb, grp);
+    float vmin = INFINITY, vmax = -INFINITY;
+    for (int t0 = 0; t0 < s; t0 += TI) {
+        const int ta = t0 + ucol;
+        const f32x4 acc = tile_dots<KC, BF16>(U, Qf, Qb, (int64_t)ta * n / s, ta < s, k, kb, grp);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int t = t0 + 4 * grp + rr;
+            if (t < s) {
+                const float v = acc[rr] + bi[(int64_t)t * n / s];
+                vmin = fminf(vmin, v);
+                vmax = fmaxf(vmax, v);
+            }
+        }
+    }
+    // the four lanes of a user: ucol, ucol + 16, ucol + 32, ucol + 48
+    vmin = fminf(vmin, __shfl_xor(vmin, 16, WAVE));
+    vmax = fmaxf(vmax, __shfl_xor(vmax, 16, WAVE));
+    vmin = fminf(vmin, __shfl_xor(vmin, 32, WAVE));
+    vmax = fmaxf(vmax, __shfl_xor(vmax, 32, WAVE));
+    const float width = vmax - vmin;
+    const float scale = width > 0.f ? (float)HBINS / width : 0.f;
+    for (int t0 = 0; t0 < s; t0 += TI) {
+        const int ta = t0 + ucol;
+        const f32x4 acc = tile_dots<KC, BF16>(U, Qf, Qb, (int64_t)ta * n / s, ta < s, k, kb, grp);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int t = t0 + 4 * grp + rr;
+            if (t < s) {
+                const float v = acc[rr] + bi[(int64_t)t * n / s];
+                const int bin = min(HBINS - 1, max(0, (int)((v - vmin) * scale)));
+                atomicAdd(&hist[ucol][bin], 1u);
+            }
+        }
+    }
+    if (lane < TU) {
+        // highest bin b with at least r scores in bins b and above
+        int acc = 0, b = HBINS - 1;
+        for (; b > 0; --b) {
+            acc += (int)hist[lane][b];
+            if (acc >= r) break;
+        }
+        const float edge = b <= 1 ? vmin : vmin + (float)(b - 1) / scale;
+        thr[tile * TU + lane] = b <= 1 ? float_to_ordered(vmin) : float_to_ordered(fminf(edge, vmax));
+    }
+}
+
+// Pass 2: every score at or above its user's threshold goes to the user's
+// candidate buffer (capg keys; the count keeps growing past capg so that
+// an overflow is seen).  Grid: user tiles x item splits.
+template <int KC, bool BF16>
+__global__ __launch_bounds__(64) void filter_kernel(const float *__restrict__ Ug, const uint16_t *__restrict__ Ugb,
+                                                    const float *__restrict__ Qf, const uint16_t *__restrict__ Qb,
+                                                    const float *__restrict__ bi, int64_t n, int k, int kp, int kb,
+                                                    int64_t per_split, const uint32_t *__restrict__ thr,
+                                                    uint32_t *__restrict__ cnt, int capg,
+                                                    uint64_t *__restrict__ cand) {
+    const int lane = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int64_t ibeg = (int64_t)blockIdx.y * per_split;
+    const int64_t iend = std::min<int64_t>(n, ibeg + per_split);
+    const int ucol = lane % 16, grp = lane / 16;
+    const int64_t urow = tile * TU + ucol;
+    UserFrag<KC, BF16> U;
+    U.load(Ug, Ugb, urow, kp, kb, grp);
+    const uint32_t t = thr[urow];
+    for (int64_t ib = ibeg; ib < iend; ib += TI) {
+        const int64_t irow = ib + ucol;
+        const f32x4 acc = tile_dots<KC, BF16>(U, Qf, Qb, irow, irow < iend, k, kb, grp);
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int64_t item = ib + 4 * grp + rr;
+            if (item < iend) {
+                const float sv = acc[rr] + bi[item];
+                if (float_to_ordered(sv) >= t) {
+                    const uint32_t pos = atomicAdd(&cnt[urow], 1u);
+                    if (pos < (uint32_t)capg) cand[urow * capg + pos] = rank_key(sv, (int32_t)item);
+                }
+            }
+        }
+    }
+}
+
+// Pass 3: one workgroup per user sorts its candidates (descending keys) and
+// writes the best `need` (0 = none).  A user with fewer than `need`
+// candidates under a real threshold, or with an overflowed buffer, is
+// marked in fail[] for the full-selection kernel.
+constexpr int FIN_WG = 256;
+constexpr int CAPG_MAX = 4096;
+
+__global__ __launch_bounds__(FIN_WG) void finish_kernel(const uint32_t *__restrict__ thr,
+                                                        const uint32_t *__restrict__ cnt,
+                                                        const uint64_t *__restrict__ cand, int capg, int need,
+                                                        uint32_t *__restrict__ fail, uint64_t *__restrict__ sel) {
+    __shared__ uint64_t buf[CAPG_MAX];
+    const int64_t row = blockIdx.x;
+    const uint32_t c = cnt[row];
+    const bool ok = c <= (uint32_t)capg && (c >= (uint32_t)need || thr[row] == 0u);
+    if (threadIdx.x == 0) fail[row] = ok ? 0u : 1u;
+    if (!ok) return;
+    const int total = (int)c;
+    for (int x = threadIdx.x; x < total; x += FIN_WG) buf[x] = cand[row * capg + x];
+    __syncthreads();
+    int N = 1;
+    while (N < total) N <<= 1;
+    for (int p = 2; p <= N; p <<= 1) {
+        const int half = p >> 1;
+        for (int idx = threadIdx.x; idx < N / 2; idx += FIN_WG) {
+            const int x = (idx / half) * p + (idx % half);
+            const int y = (idx / half) * p + p - 1 - (idx % half);
+            if (y < total) {
+                const uint64_t a = buf[x], b2 = buf[y];
+                if (a < b2) {
+                    buf[x] = b2;
+                    buf[y] = a;
+                }
+            }
+        }
+        __syncthreads();
+        for (int q = half >> 1; q >= 1; q >>= 1) {
+            for (int idx = threadIdx.x; idx < N / 2; idx += FIN_WG) {
+                const int x = (idx / q) * 2 * q + (idx % q);
+                const int y = x + q;
+                if (y < total) {
+                    const uint64_t a = buf[x], b2 = buf[y];
+                    if (a < b2) {
+                        buf[x] = b2;
+                        buf[y] = a;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int j = threadIdx.x; j < need; j += FIN_WG) sel[row * need + j] = j < total ? buf[j] : 0ull;
+}
+
+// Full selection for the users marked in fail[] (all items): each score is
+// compared with the user's running K-th best and survivors go to an LDS
+// buffer that is sorted and cut to K when it fills.  One wave per 16-user
+// tile; a tile with no marked user returns at once.
+template <int KC, int CAP, bool BF16>
+__global__ __launch_bounds__(64) void score_select_kernel(const float *__restrict__ Ug, const uint16_t *__restrict__ Ugb,
+                                                          const float *__restrict__ Qf,
+                                                          const uint16_t *__restrict__ Qb,
+                                                          const float *__restrict__ bi, int64_t n, int k, int kp,
+                                                          int kb, int K, const uint32_t *__restrict__ fail,
+                                                          uint64_t *__restrict__ out) {
+    __shared__ SelShared<CAP> sh;
+    const int lane = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    const int ucol = lane % 16, grp = lane / 16;
+    const int64_t urow = tile * TU + ucol;
+    if (__ballot(lane < TU && fail[tile * TU + lane] != 0u) == 0ull) return;
+
+    if (lane < TU) sh.cnt[lane] = 0;
+    float thr = -INFINITY;  // threshold of user ucol
+    UserFrag<KC, BF16> U;
+    U.load(Ug, Ugb, urow, kp, kb, grp);
+
+    for (int64_t ib = 0; ib < n; ib += TI) {
+        const int64_t irow = ib + ucol;
+        const f32x4 acc = tile_dots<KC, BF16>(U, Qf, Qb, irow, irow < n, k, kb, grp);
         // lane holds items ib + 4*grp + r for user ucol
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t item = ib + 4 * grp + r;
-            if (item < iend) {
+            if (item < n) {
                 const float s = acc[r] + bi[item];
                 if (s > thr) {
                     const int pos = atomicAdd(&sh.cnt[ucol], 1);
@@ -206,60 +406,15 @@ __global__ __launch_bounds__(64) void score_select_kernel(const float *__restric
             if (ucol == uu) thr = t;
         }
     }
-    // final: sort every user's buffer and emit K keys (0 = empty)
+    // final: sort every marked user's buffer and emit K keys (0 = empty)
     for (int uu = 0; uu < TU; ++uu) {
+        const int64_t row = tile * TU + uu;
+        if (fail[row] == 0u) continue;
         const int c = sh.cnt[uu];
         wave_sort_desc(sh.cand[uu], c);
-        const int64_t row = tile * TU + uu;
-        uint64_t *o = out + (row * S + split) * (int64_t)K;
+        uint64_t *o = out + row * (int64_t)K;
         for (int j = lane; j < K; j += WAVE) o[j] = j < c ? sh.cand[uu][j] : 0ull;
     }
-}
-
-// Merge the S partial lists of each user (S*K keys, each list already
-// sorted) into the best Kout keys.  One workgroup per user.
-constexpr int MERGE_WG = 256;
-constexpr int MERGE_CAP = 8192;
-
-__global__ __launch_bounds__(MERGE_WG) void merge_kernel(const uint64_t *__restrict__ part, int S, int K, int Kout,
-                                                         uint64_t *__restrict__ out) {
-    __shared__ uint64_t buf[MERGE_CAP];
-    const int64_t row = blockIdx.x;
-    const int total = S * K;
-    for (int x = threadIdx.x; x < total; x += MERGE_WG) buf[x] = part[row * total + x];
-    __syncthreads();
-    int N = 1;
-    while (N < total) N <<= 1;
-    for (int p = 2; p <= N; p <<= 1) {
-        const int half = p >> 1;
-        for (int idx = threadIdx.x; idx < N / 2; idx += MERGE_WG) {
-            const int x = (idx / half) * p + (idx % half);
-            const int y = (idx / half) * p + p - 1 - (idx % half);
-            if (y < total) {
-                const uint64_t a = buf[x], c = buf[y];
-                if (a < c) {
-                    buf[x] = c;
-                    buf[y] = a;
-                }
-            }
-        }
-        __syncthreads();
-        for (int q = half >> 1; q >= 1; q >>= 1) {
-            for (int idx = threadIdx.x; idx < N / 2; idx += MERGE_WG) {
-                const int x = (idx / q) * 2 * q + (idx % q);
-                const int y = x + q;
-                if (y < total) {
-                    const uint64_t a = buf[x], c = buf[y];
-                    if (a < c) {
-                        buf[x] = c;
-                        buf[y] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int j = threadIdx.x; j < Kout; j += MERGE_WG) out[row * Kout + j] = j < total ? buf[j] : 0ull;
 }
 
 // FP32 rescore of Kc candidates per user, then the best K.  One wave per
@@ -324,37 +479,63 @@ static int cap_for(int K) {
     return 1024;
 }
 
+// Pass kernels of one request for the given latent chunk count KC.
 template <int KC, bool BF16>
-static void launch_select(int cap, dim3 grid, const float *Ug, const uint16_t *Ugb, const float *Qf, const uint16_t *Qb,
-                          const float *bi, int64_t n, int k, int kp, int kb, int K, int64_t per_split, int S,
-                          uint64_t *out, hipStream_t s) {
-    switch (cap) {
+static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ugb, const float *Qf,
+                          const uint16_t *Qb, const float *bi, int64_t n, int k, uint32_t *thr, uint32_t *cnt,
+                          uint32_t *fail, uint64_t *cand, uint64_t *sel, hipStream_t s) {
+    const unsigned tiles = (unsigned)(T.nu_pad / TU);
+    sample_threshold_kernel<KC, BF16><<<tiles, 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb, T.s, T.r, thr, cnt);
+    BMF_HIP(hipGetLastError());
+    filter_kernel<KC, BF16><<<dim3(tiles, (unsigned)T.S), 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb,
+                                                                     T.per_split, thr, cnt, T.capg, cand);
+    BMF_HIP(hipGetLastError());
+    finish_kernel<<<(unsigned)T.nu_pad, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, fail, sel);
+    BMF_HIP(hipGetLastError());
+    switch (cap_for(T.Ksel)) {
     case 256:
-        score_select_kernel<KC, 256, BF16><<<grid, 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, kp, kb, K, per_split, S, out);
+        score_select_kernel<KC, 256, BF16><<<tiles, 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb, T.Ksel, fail, sel);
         break;
     case 512:
-        score_select_kernel<KC, 512, BF16><<<grid, 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, kp, kb, K, per_split, S, out);
+        score_select_kernel<KC, 512, BF16><<<tiles, 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb, T.Ksel, fail, sel);
         break;
     default:
-        score_select_kernel<KC, 1024, BF16><<<grid, 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, kp, kb, K, per_split, S, out);
+        score_select_kernel<KC, 1024, BF16><<<tiles, 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb, T.Ksel, fail,
+                                                                 sel);
         break;
     }
     BMF_HIP(hipGetLastError());
 }
 
 template <bool BF16>
-static void select_dispatch(int kc, int cap, dim3 grid, const float *Ug, const uint16_t *Ugb, const float *Qf,
-                            const uint16_t *Qb, const float *bi, int64_t n, int k, int kp, int kb, int K,
-                            int64_t per_split, int S, uint64_t *out, hipStream_t s) {
+static void passes_dispatch(int kc, const TopkPlan &T, const float *Ug, const uint16_t *Ugb, const float *Qf,
+                            const uint16_t *Qb, const float *bi, int64_t n, int k, uint32_t *thr, uint32_t *cnt,
+                            uint32_t *fail, uint64_t *cand, uint64_t *sel, hipStream_t s) {
     switch (kc) {
-    case 1: launch_select<1, BF16>(cap, grid, Ug, Ugb, Qf, Qb, bi, n, k, kp, kb, K, per_split, S, out, s); break;
-    case 2: launch_select<2, BF16>(cap, grid, Ug, Ugb, Qf, Qb, bi, n, k, kp, kb, K, per_split, S, out, s); break;
+    case 1: launch_passes<1, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, thr, cnt, fail, cand, sel, s); break;
+    case 2: launch_passes<2, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, thr, cnt, fail, cand, sel, s); break;
     case 3:
-    case 4: launch_select<4, BF16>(cap, grid, Ug, Ugb, Qf, Qb, bi, n, k, kp, kb, K, per_split, S, out, s); break;
+    case 4: launch_passes<4, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, thr, cnt, fail, cand, sel, s); break;
     case 5: case 6: case 7:
-    case 8: launch_select<8, BF16>(cap, grid, Ug, Ugb, Qf, Qb, bi, n, k, kp, kb, K, per_split, S, out, s); break;
-    default: launch_select<16, BF16>(cap, grid, Ug, Ugb, Qf, Qb, bi, n, k, kp, kb, K, per_split, S, out, s); break;
+    case 8: launch_passes<8, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, thr, cnt, fail, cand, sel, s); break;
+    default: launch_passes<16, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, thr, cnt, fail, cand, sel, s); break;
     }
+}
+
+// Smallest r with P(Poisson(lambda) >= r) <= eps: a sample of s items out of
+// n holds about lambda = need * s / n of the best `need` items, so the r-th
+// best sampled score is at most the need-th best overall except with
+// probability eps.
+static int sample_rank(double lambda, double eps) {
+    if (lambda > 50.0) return (int)std::ceil(lambda + 5.0 * std::sqrt(lambda));  // normal tail, about 3e-7
+    double term = std::exp(-lambda), cdf = term;  // P(X <= 0)
+    int r = 1;
+    while (1.0 - cdf > eps && r < 1 << 20) {
+        term *= lambda / r;  // P(X = r)
+        cdf += term;
+        ++r;
+    }
+    return r;
 }
 
 void ensure_bf16_items(Model &M) {
@@ -377,13 +558,29 @@ TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
     T.kp = round_up(M.k, 16);
     T.kb = round_up(M.k, 32);
     T.nu_pad = (nu + TU - 1) / TU * TU;
+    const int64_t n = M.n;
+    const int need = T.Ksel;
+    if (need >= n || n <= SAMPLE_MAX) {
+        // every item is a candidate
+        T.s = 0;
+        T.r = 0;
+        T.capg = round_up((int)n, 64);
+    } else {
+        T.s = SAMPLE_MAX;
+        T.r = std::min(T.s, sample_rank((double)need * T.s / (double)n, 1e-6));
+        // candidates expected above the r-th best of the sample: r / (s + 1)
+        // of the items; three times that plus slack makes an overflow (which
+        // falls back to the full selection) rarer than about 1e-6
+        const double expect = (double)T.r / (T.s + 1) * (double)n;
+        T.capg = std::min(CAPG_MAX, round_up((int)std::min(3.0 * expect + 128.0, (double)CAPG_MAX), 64));
+        T.capg = std::max(T.capg, std::min(CAPG_MAX, round_up(need + 64, 64)));
+    }
+    // item splits for the filter: enough workgroups to fill the chip
     const int64_t tiles = T.nu_pad / TU;
-    // item splits: enough workgroups to fill the chip, merged afterwards
-    int S = (int)std::max<int64_t>(1, (2048 + tiles - 1) / std::max<int64_t>(tiles, 1));
-    S = (int)std::min<int64_t>(S, std::max<int64_t>(1, M.n / 256));
-    S = std::min(S, std::max(1, MERGE_CAP / T.Ksel));
-    T.per_split = ((M.n + S - 1) / S + TI - 1) / TI * TI;
-    T.S = (int)std::max<int64_t>(1, (M.n + T.per_split - 1) / T.per_split);
+    int S = (int)std::max<int64_t>(1, (4096 + tiles - 1) / std::max<int64_t>(tiles, 1));
+    S = (int)std::min<int64_t>(S, std::max<int64_t>(1, n / 256));
+    T.per_split = ((n + S - 1) / S + TI - 1) / TI * TI;
+    T.S = (int)std::max<int64_t>(1, (n + T.per_split - 1) / T.per_split);
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -393,7 +590,10 @@ TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
     T.off_ug = take((size_t)T.nu_pad * T.kp * 4);
     T.off_ugb = take((size_t)T.nu_pad * T.kb * 2);
     T.off_ub = take((size_t)T.nu_pad * 4);
-    T.off_part = take((size_t)T.nu_pad * T.S * T.Ksel * 8);
+    T.off_thr = take((size_t)T.nu_pad * 4);
+    T.off_cnt = take((size_t)T.nu_pad * 4);
+    T.off_fail = take((size_t)T.nu_pad * 4);
+    T.off_cand = take((size_t)T.nu_pad * std::max(T.capg, T.K) * 8);
     T.off_sel = take((size_t)T.nu_pad * std::max(T.Ksel, T.K) * 8);
     T.total = o;
     return T;
@@ -413,30 +613,25 @@ void topk_score(Model &M, const TopkPlan &T, unsigned char *work, int32_t *d_ite
     const float *Ug = reinterpret_cast<const float *>(work + T.off_ug);
     const uint16_t *Ugb = reinterpret_cast<const uint16_t *>(work + T.off_ugb);
     const float *ub = reinterpret_cast<const float *>(work + T.off_ub);
-    uint64_t *part = reinterpret_cast<uint64_t *>(work + T.off_part);
+    uint32_t *thr = reinterpret_cast<uint32_t *>(work + T.off_thr);
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(work + T.off_cnt);
+    uint32_t *fail = reinterpret_cast<uint32_t *>(work + T.off_fail);
+    uint64_t *cand = reinterpret_cast<uint64_t *>(work + T.off_cand);
     uint64_t *sel = reinterpret_cast<uint64_t *>(work + T.off_sel);
-    const int cap = cap_for(T.Ksel);
-    const dim3 grid((unsigned)(T.nu_pad / TU), (unsigned)T.S);
     if (T.bf) {
         if (!M.bf16_valid) BMF_FAIL(BMF_E_STATE, "BF16 item table not prepared");
-        select_dispatch<true>(T.kb / 32, cap, grid, Ug, Ugb, M.Q.as<float>(), M.Qb.as<uint16_t>(), M.bi.as<float>(),
-                              M.n, M.k, T.kp, T.kb, T.Ksel, T.per_split, T.S, part, s);
+        passes_dispatch<true>(T.kb / 32, T, Ug, Ugb, M.Q.as<float>(), M.Qb.as<uint16_t>(), M.bi.as<float>(), M.n, M.k,
+                              thr, cnt, fail, cand, sel, s);
     } else {
-        select_dispatch<false>(T.kp / 16, cap, grid, Ug, Ugb, M.Q.as<float>(), nullptr, M.bi.as<float>(), M.n, M.k,
-                               T.kp, T.kb, T.Ksel, T.per_split, T.S, part, s);
+        passes_dispatch<false>(T.kp / 16, T, Ug, Ugb, M.Q.as<float>(), nullptr, M.bi.as<float>(), M.n, M.k, thr, cnt,
+                               fail, cand, sel, s);
     }
-    const uint64_t *cand = part;
-    if (T.S > 1) {
-        merge_kernel<<<(unsigned)T.nu, MERGE_WG, 0, s>>>(part, T.S, T.Ksel, T.Ksel, sel);
-        BMF_HIP(hipGetLastError());
-        cand = sel;
-    }
-    const uint64_t *fin = cand;
+    const uint64_t *fin = sel;
     if (T.bf) {
-        uint64_t *dst = (cand == sel) ? part : sel;
+        uint64_t *dst = cand;  // the candidate buffers are free again
         const int kpl = (M.k + 63) / 64;
 #define RS_LAUNCH(KPL)                                                                                              \
-    rescore_kernel<KPL><<<(unsigned)T.nu, 64, 0, s>>>(cand, T.Ksel, T.K, Ug, T.kp, M.Q.as<float>(), M.bi.as<float>(), \
+    rescore_kernel<KPL><<<(unsigned)T.nu, 64, 0, s>>>(sel, T.Ksel, T.K, Ug, T.kp, M.Q.as<float>(), M.bi.as<float>(), \
                                                       M.k, dst)
         switch (kpl) {
         case 1: RS_LAUNCH(1); break;

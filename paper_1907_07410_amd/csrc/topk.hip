@@ -150,41 +150,69 @@ struct UserFrag {
     }
 };
 
-// Dot products of a 16-item x 16-user tile: this lane feeds item row `irow`
-// (when irow_ok) into the A operand and receives, in acc[r], the score of
-// user (lane % 16) with item (tile item 4 * (lane / 16) + r).
+// A operand of a 16-item tile: this lane's part of item row `irow` (zero
+// when !irow_ok).  Split from the MFMAs so that loops can load the next
+// tile while the current one is multiplied.
 template <int KC, bool BF16>
-__device__ __forceinline__ f32x4 tile_dots(const UserFrag<KC, BF16> &U, const float *__restrict__ Qf,
-                                           const uint16_t *__restrict__ Qb, int64_t irow, bool irow_ok, int k,
-                                           int kb, int grp) {
+struct ItemFrag {
+    f32x4 f[BF16 ? 1 : KC];
+    uint4 b[BF16 ? KC : 1];
+    __device__ __forceinline__ void load(const float *__restrict__ Qf, const uint16_t *__restrict__ Qb, int64_t irow,
+                                         bool irow_ok, int k, int kb, int grp) {
+        if (!BF16) {
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                f32x4 a = {0.f, 0.f, 0.f, 0.f};
+                const int f0 = c * 16 + 4 * grp;
+                if (irow_ok) {
+                    if (f0 + 3 < k && (k & 3) == 0) {
+                        a = *reinterpret_cast<const f32x4 *>(Qf + irow * k + f0);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) a[e] = (f0 + e < k) ? Qf[irow * k + f0 + e] : 0.f;
+                    }
+                }
+                f[c] = a;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                uint4 raw = {0u, 0u, 0u, 0u};
+                if (irow_ok && c * 32 < kb) raw = *reinterpret_cast<const uint4 *>(Qb + irow * kb + c * 32 + 8 * grp);
+                b[c] = raw;
+            }
+        }
+    }
+};
+
+// Dot products of a 16-item x 16-user tile: acc[r] = score of user
+// (lane % 16) with item (tile item 4 * (lane / 16) + r).
+template <int KC, bool BF16>
+__device__ __forceinline__ f32x4 tile_mma(const UserFrag<KC, BF16> &U, const ItemFrag<KC, BF16> &A) {
     f32x4 acc = {0.f, 0.f, 0.f, 0.f};
     if (!BF16) {
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
-            f32x4 a = {0.f, 0.f, 0.f, 0.f};
-            const int f0 = c * 16 + 4 * grp;
-            if (irow_ok) {
-                if (f0 + 3 < k && (k & 3) == 0) {
-                    a = *reinterpret_cast<const f32x4 *>(Qf + irow * k + f0);
-                } else {
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) a[e] = (f0 + e < k) ? Qf[irow * k + f0 + e] : 0.f;
-                }
-            }
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], U.f[c][0], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], U.f[c][1], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], U.f[c][2], acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], U.f[c][3], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A.f[c][0], U.f[c][0], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A.f[c][1], U.f[c][1], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A.f[c][2], U.f[c][2], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A.f[c][3], U.f[c][3], acc, 0, 0, 0);
         }
     } else {
 #pragma unroll
-        for (int c = 0; c < KC; ++c) {
-            uint4 raw = {0u, 0u, 0u, 0u};
-            if (irow_ok && c * 32 < kb) raw = *reinterpret_cast<const uint4 *>(Qb + irow * kb + c * 32 + 8 * grp);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, raw), U.b[c], acc, 0, 0, 0);
-        }
+        for (int c = 0; c < KC; ++c)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A.b[c]), U.b[c], acc, 0, 0, 0);
     }
     return acc;
+}
+
+template <int KC, bool BF16>
+__device__ __forceinline__ f32x4 tile_dots(const UserFrag<KC, BF16> &U, const float *__restrict__ Qf,
+                                           const uint16_t *__restrict__ Qb, int64_t irow, bool irow_ok, int k,
+                                           int kb, int grp) {
+    ItemFrag<KC, BF16> A;
+    A.load(Qf, Qb, irow, irow_ok, k, kb, grp);
+    return tile_mma(U, A);
 }
 
 constexpr int SAMPLE_MAX = 1024;
@@ -196,71 +224,90 @@ constexpr int HBINS = 256;
 // threshold is the lower edge of the bin below the one holding the r-th best
 // sampled score (so at least r sampled scores reach it, whatever the
 // rounding of the bin index).  Stored as an ordered key; 0 = no threshold
-// (r = 0).  Also clears the user's candidate count.  One wave per 16-user
-// tile; lane (u, g) handles user u and a quarter of each sample tile.
+// (r = 0).  Also clears the user's candidate count.  One workgroup of
+// SMP_WAVES waves per 16-user tile, each wave taking every SMP_WAVES-th
+// sample tile; lane (u, g) of a wave handles user u.
+constexpr int SMP_WAVES = 4;
+
 template <int KC, bool BF16>
-__global__ __launch_bounds__(64) void sample_threshold_kernel(const float *__restrict__ Ug,
-                                                              const uint16_t *__restrict__ Ugb,
-                                                              const float *__restrict__ Qf,
-                                                              const uint16_t *__restrict__ Qb,
-                                                              const float *__restrict__ bi, int64_t n, int k, int kp,
-                                                              int kb, int s, int r, uint32_t *__restrict__ thr,
-                                                              uint32_t *__restrict__ cnt) {
+__global__ __launch_bounds__(SMP_WAVES *WAVE) void sample_threshold_kernel(
+    const float *__restrict__ Ug, const uint16_t *__restrict__ Ugb, const float *__restrict__ Qf,
+    const uint16_t *__restrict__ Qb, const float *__restrict__ bi, int64_t n, int k, int kp, int kb, int s, int r,
+    uint32_t *__restrict__ thr, uint32_t *__restrict__ cnt) {
     __shared__ uint32_t hist[TU][HBINS];
-    const int lane = threadIdx.x;
+    __shared__ float ext[SMP_WAVES][2][TU];
+    const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
     const int64_t tile = blockIdx.x;
     const int ucol = lane % 16, grp = lane / 16;
-    if (lane < TU) cnt[tile * TU + lane] = 0u;
+    if (tid < TU) cnt[tile * TU + tid] = 0u;
     if (r == 0) {
-        if (lane < TU) thr[tile * TU + lane] = 0u;
+        if (tid < TU) thr[tile * TU + tid] = 0u;
         return;
     }
-    for (int x = lane; x < TU * HBINS; x += WAVE) (&hist[0][0])[x] = 0u;
+    for (int x = tid; x < TU * HBINS; x += SMP_WAVES * WAVE) (&hist[0][0])[x] = 0u;
     UserFrag<KC, BF16> U;
     U.load(Ug, Ugb, tile * TU + ucol, kp, kb, grp);
-    float vmin = INFINITY, vmax = -INFINITY;
-    for (int t0 = 0; t0 < s; t0 += TI) {
-        const int ta = t0 + ucol;
-        const f32x4 acc = tile_dots<KC, BF16>(U, Qf, Qb, (int64_t)ta * n / s, ta < s, k, kb, grp);
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int t = t0 + 4 * grp + rr;
-            if (t < s) {
-                const float v = acc[rr] + bi[(int64_t)t * n / s];
-                vmin = fminf(vmin, v);
-                vmax = fmaxf(vmax, v);
-            }
+    const int step = SMP_WAVES * TI;
+    // scores of this wave's sample tiles, with the next tile's rows loaded
+    // while the current one is multiplied; f(t, v) is called for every
+    // sample index t < s of the tile and its score v
+    auto sweep = [&](auto &&f) {
+        ItemFrag<KC, BF16> A, An;
+        int t0 = wave * TI;
+        {
+            const int ta = t0 + ucol;
+            A.load(Qf, Qb, (int64_t)ta * n / s, ta < s, k, kb, grp);
         }
-    }
-    // the four lanes of a user: ucol, ucol + 16, ucol + 32, ucol + 48
+        for (; t0 < s; t0 += step) {
+            const int tn = t0 + step + ucol;
+            An.load(Qf, Qb, (int64_t)tn * n / s, tn < s, k, kb, grp);
+            const f32x4 acc = tile_mma(U, A);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int t = t0 + 4 * grp + rr;
+                if (t < s) f(t, acc[rr] + bi[(int64_t)t * n / s]);
+            }
+            A = An;
+        }
+    };
+    float vmin = INFINITY, vmax = -INFINITY;
+    sweep([&](int, float v) {
+        vmin = fminf(vmin, v);
+        vmax = fmaxf(vmax, v);
+    });
+    // the four lanes of a user (ucol + 16 g), then the waves
     vmin = fminf(vmin, __shfl_xor(vmin, 16, WAVE));
     vmax = fmaxf(vmax, __shfl_xor(vmax, 16, WAVE));
     vmin = fminf(vmin, __shfl_xor(vmin, 32, WAVE));
     vmax = fmaxf(vmax, __shfl_xor(vmax, 32, WAVE));
+    if (lane < TU) {
+        ext[wave][0][lane] = vmin;
+        ext[wave][1][lane] = vmax;
+    }
+    __syncthreads();
+    vmin = ext[0][0][ucol];
+    vmax = ext[0][1][ucol];
+#pragma unroll
+    for (int w = 1; w < SMP_WAVES; ++w) {
+        vmin = fminf(vmin, ext[w][0][ucol]);
+        vmax = fmaxf(vmax, ext[w][1][ucol]);
+    }
     const float width = vmax - vmin;
     const float scale = width > 0.f ? (float)HBINS / width : 0.f;
-    for (int t0 = 0; t0 < s; t0 += TI) {
-        const int ta = t0 + ucol;
-        const f32x4 acc = tile_dots<KC, BF16>(U, Qf, Qb, (int64_t)ta * n / s, ta < s, k, kb, grp);
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int t = t0 + 4 * grp + rr;
-            if (t < s) {
-                const float v = acc[rr] + bi[(int64_t)t * n / s];
-                const int bin = min(HBINS - 1, max(0, (int)((v - vmin) * scale)));
-                atomicAdd(&hist[ucol][bin], 1u);
-            }
-        }
-    }
-    if (lane < TU) {
+    sweep([&](int, float v) {
+        const int bin = min(HBINS - 1, max(0, (int)((v - vmin) * scale)));
+        atomicAdd(&hist[ucol][bin], 1u);
+    });
+    __syncthreads();
+    if (tid < TU) {
         // highest bin b with at least r scores in bins b and above
         int acc = 0, b = HBINS - 1;
         for (; b > 0; --b) {
-            acc += (int)hist[lane][b];
+            acc += (int)hist[tid][b];
             if (acc >= r) break;
         }
-        const float edge = b <= 1 ? vmin : vmin + (float)(b - 1) / scale;
-        thr[tile * TU + lane] = b <= 1 ? float_to_ordered(vmin) : float_to_ordered(fminf(edge, vmax));
+        const float edge = vmin + (float)(b - 1) / scale;
+        thr[tile * TU + tid] = b <= 1 ? float_to_ordered(vmin) : float_to_ordered(fminf(edge, vmax));
     }
 }
 
@@ -283,9 +330,13 @@ __global__ __launch_bounds__(64) void filter_kernel(const float *__restrict__ Ug
     UserFrag<KC, BF16> U;
     U.load(Ug, Ugb, urow, kp, kb, grp);
     const uint32_t t = thr[urow];
+    ItemFrag<KC, BF16> A, An;
+    A.load(Qf, Qb, ibeg + ucol, ibeg + ucol < iend, k, kb, grp);
     for (int64_t ib = ibeg; ib < iend; ib += TI) {
-        const int64_t irow = ib + ucol;
-        const f32x4 acc = tile_dots<KC, BF16>(U, Qf, Qb, irow, irow < iend, k, kb, grp);
+        const int64_t inext = ib + TI + ucol;  // next tile's row, loaded while this one is multiplied
+        An.load(Qf, Qb, inext, inext < iend, k, kb, grp);
+        const f32x4 acc = tile_mma(U, A);
+        A = An;
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
             const int64_t item = ib + 4 * grp + rr;
@@ -485,7 +536,7 @@ static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ug
                           const uint16_t *Qb, const float *bi, int64_t n, int k, uint32_t *thr, uint32_t *cnt,
                           uint32_t *fail, uint64_t *cand, uint64_t *sel, hipStream_t s) {
     const unsigned tiles = (unsigned)(T.nu_pad / TU);
-    sample_threshold_kernel<KC, BF16><<<tiles, 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb, T.s, T.r, thr, cnt);
+    sample_threshold_kernel<KC, BF16><<<tiles, SMP_WAVES * WAVE, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb, T.s, T.r, thr, cnt);
     BMF_HIP(hipGetLastError());
     filter_kernel<KC, BF16><<<dim3(tiles, (unsigned)T.S), 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb,
                                                                      T.per_split, thr, cnt, T.capg, cand);

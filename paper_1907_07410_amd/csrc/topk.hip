@@ -469,38 +469,40 @@ __global__ __launch_bounds__(64) void score_select_kernel(const float *__restric
 }
 
 // FP32 rescore of Kc candidates per user, then the best K.  One wave per
-// user; lane f owns factors f, f+64, ...; each candidate's dot product is a
-// fixed-order butterfly (same every call).
-template <int KPL>
+// user; lane j takes candidates j, j + 64, ... and sums its dot product over
+// the factors in index order (one fma chain; the same every call), reading
+// the user's row from LDS.
 __global__ __launch_bounds__(64) void rescore_kernel(const uint64_t *__restrict__ cand, int Kc, int K,
                                                      const float *__restrict__ Ug, int kp,
                                                      const float *__restrict__ Qf, const float *__restrict__ bi,
                                                      int k, uint64_t *__restrict__ out) {
     __shared__ uint64_t buf[2048];
+    __shared__ __align__(16) float pu[256];
     const int64_t row = blockIdx.x;
     const int lane = threadIdx.x;
-    float p[KPL];
-#pragma unroll
-    for (int c = 0; c < KPL; ++c) {
-        const int f = lane + WAVE * c;
-        p[c] = f < k ? Ug[row * kp + f] : 0.f;
-    }
-    for (int j = 0; j < Kc; ++j) {
+    for (int f = lane; f < kp; f += WAVE) pu[f] = Ug[row * kp + f];
+    const bool vec = (k & 3) == 0;
+    for (int j = lane; j < Kc; j += WAVE) {
         const uint64_t key = cand[row * Kc + j];
         uint64_t nk = 0ull;
         if (key != 0ull) {
             const int32_t item = key_item(key);
+            const float *q = Qf + (int64_t)item * k;
             float d = 0.f;
-#pragma unroll
-            for (int c = 0; c < KPL; ++c) {
-                const int f = lane + WAVE * c;
-                const float qv = f < k ? Qf[(int64_t)item * k + f] : 0.f;
-                d = c == 0 ? p[c] * qv : fmaf(p[c], qv, d);
+            if (vec) {
+                for (int f = 0; f < k; f += 4) {
+                    const float4 qv = *reinterpret_cast<const float4 *>(q + f);
+                    d = f == 0 ? pu[0] * qv.x : fmaf(pu[f], qv.x, d);
+                    d = fmaf(pu[f + 1], qv.y, d);
+                    d = fmaf(pu[f + 2], qv.z, d);
+                    d = fmaf(pu[f + 3], qv.w, d);
+                }
+            } else {
+                for (int f = 0; f < k; ++f) d = f == 0 ? pu[0] * q[0] : fmaf(pu[f], q[f], d);
             }
-            d = wave_sum_xor(d);
             nk = rank_key(d + bi[item], item);
         }
-        if (lane == 0) buf[j] = nk;
+        buf[j] = nk;
     }
     wave_sort_desc(buf, Kc);
     for (int j = lane; j < K; j += WAVE) out[row * K + j] = j < Kc ? buf[j] : 0ull;
@@ -680,17 +682,8 @@ void topk_score(Model &M, const TopkPlan &T, unsigned char *work, int32_t *d_ite
     const uint64_t *fin = sel;
     if (T.bf) {
         uint64_t *dst = cand;  // the candidate buffers are free again
-        const int kpl = (M.k + 63) / 64;
-#define RS_LAUNCH(KPL)                                                                                              \
-    rescore_kernel<KPL><<<(unsigned)T.nu, 64, 0, s>>>(sel, T.Ksel, T.K, Ug, T.kp, M.Q.as<float>(), M.bi.as<float>(), \
-                                                      M.k, dst)
-        switch (kpl) {
-        case 1: RS_LAUNCH(1); break;
-        case 2: RS_LAUNCH(2); break;
-        case 3: RS_LAUNCH(3); break;
-        default: RS_LAUNCH(4); break;
-        }
-#undef RS_LAUNCH
+        rescore_kernel<<<(unsigned)T.nu, 64, 0, s>>>(sel, T.Ksel, T.K, Ug, T.kp, M.Q.as<float>(), M.bi.as<float>(), M.k,
+                                                    dst);
         BMF_HIP(hipGetLastError());
         fin = dst;
     }

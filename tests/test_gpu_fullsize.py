@@ -1,8 +1,18 @@
-"""Full-size parity on the mid-scale workload (138,000 x 27,000, 18M
-training ratings, k=64, 64 x 64 blocks) in the launch configuration the
-benchmark times: partition bit-exact, factors within 1e-4 after one epoch,
-test RMSE within 1e-3 after 20 epochs.  The oracle runs its threaded stratum
-mode (identical results for any thread count)."""
+"""Full-size parity.
+
+Mid-scale workload (138,000 x 27,000, 18M training ratings, k=64, 64 x 64
+blocks) in the launch configuration the benchmark times: partition
+bit-exact, factors within 1e-4 after one epoch, test RMSE within 1e-3 after
+20 epochs.
+
+Large-scale workload (480,000 x 17,800, 90M training ratings, k=128,
+128 x 128 blocks): partition bit-exact, factors within 1e-4 after one
+epoch, then top-100 for 20,000 users in FP32 (every answer epsilon-valid
+against FP64 scores on sampled users) and in BF16 with FP32 rescoring
+(recall@100 against FP32 of at least 0.99).
+
+The oracle runs its threaded stratum mode (identical results for any thread
+count)."""
 import os
 import sys
 
@@ -51,3 +61,38 @@ def test_mid_scale_parity(orc, mid):
     tg, to = G.rmse(), O.rmse()
     log("20 epochs train rmse gpu", tg, "oracle", to)
     assert abs(tg - to) <= 1e-3
+
+
+def test_large_scale_parity_and_bf16_scoring(orc):
+    from paper_1907_07410_amd import binding as B
+    from test_gpu_parity import eps_valid
+    cfg = configs.LARGE
+    large = cfg.generate(1)
+    tr = large.train
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    log("large-scale: loading", len(tr), "ratings")
+    G = B.Model(large.m, large.n, cfg.k, cfg.b, seed=1001, order_mode=0)
+    G.load_ratings(tr.u, tr.i, tr.r)
+    O = orc.Model(large.m, large.n, cfg.k, cfg.b, seed=1001, order_mode=0)
+    O.load(tr.u, tr.i, tr.r)
+    bp, perm = G.get_partition(len(tr))
+    assert np.array_equal(bp, O.block_ptr) and np.array_equal(perm, O.perm)
+    log("partition bit-exact")
+    G.epoch(cfg.lr, cfg.reg)
+    O.epoch(cfg.lr, cfg.reg, threads=threads)
+    P, Q, bu, bi, mu = G.get_factors()
+    d = max(np.abs(P - O.P).max(), np.abs(Q - O.Q).max(), np.abs(bu - O.bu).max(), np.abs(bi - O.bi).max())
+    log("one epoch max abs diff", d)
+    assert d <= 1e-4
+    del O
+    rng = np.random.default_rng(3)
+    users = rng.choice(large.m, 20000, replace=False).astype(np.int32)
+    K = 100
+    fi, fs = G.topk(users, K)
+    bi_, bs = G.topk_bf16(users, K)
+    recall = float(np.mean([len(set(a) & set(b)) / K for a, b in zip(fi, bi_)]))
+    log("large-scale bf16 recall@100 vs fp32 over", len(users), "users:", recall)
+    assert recall >= 0.99
+    pick = rng.choice(len(users), 24, replace=False)
+    eps_valid(fi[pick], fs[pick], P, Q, bu, bi, mu, users[pick], K, (cfg.k + 8) * 2.0 ** -23)
+    eps_valid(bi_[pick], bs[pick], P, Q, bu, bi, mu, users[pick], K, (cfg.k + 8) * 2.0 ** -23)

@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}  # MI355X dense matrix peaks
 
 # HBM bytes per launch of the SGD stratum kernel on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors
@@ -239,12 +240,16 @@ def main():
     G.synchronize()
     G.sgd_timing(reset=True)
 
+    # test ratings resident on the device for the timed steps
+    tu = torch.from_numpy(te.u).cuda()
+    ti = torch.from_numpy(te.i).cuda()
+    tr_ = torch.from_numpy(te.r).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rmse = None
     for _ in range(args.steps):
         G.epoch(cfg.lr, cfg.reg)
-        rmse = G.rmse(te.u, te.i, te.r)
+        rmse = G.rmse_dev(tu, ti, tr_)
     G.synchronize()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
@@ -254,20 +259,59 @@ def main():
     achieved = (abytes / cfg.b) / (per_launch_ms / 1e3) / 1e9
     log(f"{args.steps} steps in {el:.3f}s; sgd kernels {sgd_ms:.2f} ms over {launches} launches; test rmse {rmse:.4f}")
 
+    # test-RMSE pass alone, timed with events on torch's stream (the
+    # library's stream is pointed at it): algorithmic bytes = the COO once
+    # (12 B) plus the user and item rows with biases ((k+1) 4 B each) per
+    # rating
+    G.synchronize()
+    ts = torch.cuda.Stream()  # a named stream: the library and the events share it
+    G.set_option(binding.OPT_STREAM, ts.cuda_stream)
+    G.rmse_dev(tu, ti, tr_)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 5
+    ev0.record(ts)
+    for _ in range(reps):
+        G.rmse_dev(tu, ti, tr_)
+    ev1.record(ts)
+    ts.synchronize()
+    rmse_ms = ev0.elapsed_time(ev1) / reps
+    rmse_bytes = len(te) * (12 + 2 * (cfg.k + 1) * 4)
+    rmse_out = {"ratings": len(te), "ms": rmse_ms, "algorithmic_bytes": rmse_bytes,
+                "achieved_GBps": rmse_bytes / (rmse_ms / 1e3) / 1e9,
+                "frac_of_hbm_peak": rmse_bytes / (rmse_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                "note": "includes the device range check and the FP64 partial-sum tree"}
+    G.set_option(binding.OPT_STREAM, 0)
+    log(f"test RMSE pass {rmse_ms:.3f} ms, {rmse_out['achieved_GBps']:.0f} GB/s algorithmic")
+
     # top-100 for a batch of users, FP32 and BF16 scoring
     topk = {}
     if args.topk_users > 0:
         rng = np.random.default_rng(7)
         users = rng.integers(0, prob.m, args.topk_users).astype(np.int32)
         res = {}
-        for name, fn in (("fp32", lambda: G.topk(users, 100)), ("bf16", lambda: G.topk_bf16(users, 100))):
-            fn()
-            t0 = time.perf_counter()
-            out = fn()
-            dt = time.perf_counter() - t0
-            res[name] = out
+        du = torch.from_numpy(users).cuda()
+        torch.cuda.synchronize()
+        G.set_option(binding.OPT_STREAM, ts.cuda_stream)
+        flops = 2.0 * len(users) * prob.n * cfg.k
+        for name, prec, peak in (("fp32", 0, MFMA_PEAK_TFLOPS["fp32"]), ("bf16", 1, MFMA_PEAK_TFLOPS["bf16"])):
+            it = torch.empty((len(users), 100), dtype=torch.int32, device="cuda")
+            sc = torch.empty((len(users), 100), dtype=torch.float32, device="cuda")
+            torch.cuda.synchronize()
+            G.topk_dev(du, 100, prec, 0, it, sc)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            reps = 5
+            ev0.record(ts)
+            for _ in range(reps):
+                G.topk_dev(du, 100, prec, 0, it, sc)
+            ev1.record(ts)
+            ts.synchronize()
+            dt = ev0.elapsed_time(ev1) / reps / 1e3
+            res[name] = (it.cpu().numpy(), sc.cpu().numpy())
             topk[name + "_users_per_s"] = len(users) / dt
             topk[name + "_ms"] = dt * 1e3
+            topk[name + "_contraction_tflops"] = flops / dt / 1e12
+            topk[name + "_frac_of_mfma_peak"] = flops / dt / 1e12 / peak
+        G.set_option(binding.OPT_STREAM, 0)
         recall = float(np.mean([len(set(a) & set(b)) / 100 for a, b in zip(res["fp32"][0], res["bf16"][0])]))
         topk["recall_at_100_bf16_vs_fp32"] = recall
         topk["users"] = len(users)
@@ -312,6 +356,7 @@ def main():
         "parity_1epoch_max_abs": parity,
         "critical_path_ratings_per_epoch": cp,
         "load_s": load_s,
+        "rmse_pass": rmse_out,
         "topk": topk,
         "serving": serving_out,
         "batched": batched_out,

@@ -184,6 +184,11 @@ bmf_status bmf_factor_ptrs(bmf_ctx *c, float **P, float **Q, float **bu, float *
  * Errors: BMF_E_RANGE for an out-of-range index; BMF_E_STATE. */
 bmf_status bmf_rmse(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r, int64_t cnt,
                     double *out);
+/* bmf_rmse over device-resident ratings (u, i, r: device pointers of cnt
+ * entries on the context's device; read only).  The ranges are checked on
+ * the device (BMF_E_RANGE names the first bad index).  Synchronises. */
+bmf_status bmf_rmse_dev(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r, int64_t cnt,
+                        double *out);
 
 /* Regularised loss over the training ratings: sum of err^2 + beta_p |p_u|^2
  * + beta_q |q_i|^2 + beta_bu bu_u^2 + beta_bi bi_i^2 at every rating (Eq 9

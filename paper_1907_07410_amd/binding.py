@@ -32,6 +32,15 @@ class BmfError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libbmf.so not built at {LIB_PATH}; run python -m paper_1907_07410_amd.build")
+    # PyTorch ships its own HIP runtime with the same soname as the system
+    # one; loading torch first makes libbmf bind to that same instance, so
+    # one HIP runtime serves both and torch device pointers and streams are
+    # valid in the library.  (Loaded the other way round, torch would start
+    # a second runtime and see no GPU.)
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     i64, i32, f32, dbl, p = C.c_int64, C.c_int32, C.c_float, C.c_double, C.c_void_p
     pp = C.POINTER(C.c_void_p)
@@ -56,6 +65,7 @@ def _load():
         "bmf_topk": ([p, p, i64, i32, p, p], i32),
         "bmf_topk_bf16": ([p, p, i64, i32, i32, p, p], i32),
         "bmf_topk_dev": ([p, p, i64, i32, i32, i32, p, p], i32),
+        "bmf_rmse_dev": ([p, p, p, p, i64, p], i32),
         "bmf_foldin": ([p, p, p, i32, i32, f32, f32, p, p], i32),
         "bmf_sgd_timing": ([p, p, p, i32], i32),
         "bmf_debug_wave_sum": ([p, p], i32),
@@ -220,6 +230,12 @@ class Model:
         else:
             u, i, r = _c(u, np.int32), _c(i, np.int32), _c(r, np.float32)
             self._check(lib.bmf_rmse(self._h, _ptr(u), _ptr(i), _ptr(r), u.shape[0], C.byref(out)))
+        return out.value
+
+    def rmse_dev(self, u, i, r) -> float:
+        """RMSE over device tensors (int32 u, i; float32 r) on the context's device."""
+        out = C.c_double()
+        self._check(lib.bmf_rmse_dev(self._h, _dptr(u), _dptr(i), _dptr(r), int(u.numel()), C.byref(out)))
         return out.value
 
     def loss(self, lr: float = 0.0, reg: float = 0.0, hp=None) -> float:

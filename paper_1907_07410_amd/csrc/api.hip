@@ -338,6 +338,18 @@ bmf_status bmf_rmse(bmf_ctx *c, const int32_t *u, const int32_t *i, const float 
     });
 }
 
+bmf_status bmf_rmse_dev(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r, int64_t cnt, double *out) {
+    return guarded(c, false, [&] {
+        Model &M = c->M;
+        if (!out) BMF_FAIL(BMF_E_INVAL, "null output");
+        if (cnt < 0 || (cnt > 0 && (!u || !i || !r))) BMF_FAIL(BMF_E_INVAL, "bad evaluation arrays");
+        const int64_t bad = validate_coo(u, i, r, cnt, M.m, M.n, M.red, M.stream);
+        if (bad >= 0) BMF_FAIL(BMF_E_RANGE, "evaluation rating " + std::to_string(bad) + " out of range");
+        const double s = cnt > 0 ? sq_residual_sum(M, u, i, r, cnt, nullptr, M.red) : 0.0;
+        *out = cnt > 0 ? std::sqrt(s / (double)cnt) : 0.0;
+    });
+}
+
 bmf_status bmf_loss(bmf_ctx *c, const float hp[8], double *out) {
     return guarded(c, false, [&] {
         Model &M = c->M;

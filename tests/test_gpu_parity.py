@@ -222,6 +222,24 @@ def test_rmse_and_loss_match_oracle_on_same_factors(B, orc):
     assert G.rmse(test.u, test.i, test.r) == pytest.approx(O.rmse(test.u, test.i, test.r), rel=1e-6)
 
 
+def test_rmse_dev_matches_host_and_checks_ranges(B):
+    import torch
+    p = configs.TINY.generate(2)
+    G = B.Model(p.m, p.n, 16, 4)
+    G.load_ratings(p.train.u, p.train.i, p.train.r)
+    G.epoch(0.01, 0.02)
+    te = p.train
+    tu = torch.from_numpy(te.u).cuda()
+    ti = torch.from_numpy(te.i).cuda()
+    tr = torch.from_numpy(te.r).cuda()
+    assert G.rmse_dev(tu, ti, tr) == G.rmse(te.u, te.i, te.r) == G.rmse()
+    bad = tu.clone()
+    bad[7] = p.m
+    with pytest.raises(B.BmfError) as ex:
+        G.rmse_dev(bad, ti, tr)
+    assert ex.value.status == B.BMF_E_RANGE
+
+
 def test_rmse_closed_form_zero_factors(B):
     p = configs.TINY.generate(3)
     G = B.Model(p.m, p.n, 16, 4)

@@ -155,6 +155,16 @@ bmf_status bmf_epoch_hp(bmf_ctx *c, const float hp[8]);
 /* Number of epochs run so far (the next epoch's index). */
 bmf_status bmf_epoch_count(const bmf_ctx *c, int32_t *out);
 
+/* Algorithm 1's loop: epochs with the pairs hp (as bmf_epoch_hp) until the
+ * training RMSE improves by less than delta over the previous epoch (the
+ * first epoch compares with the RMSE before it), at most max_epochs.
+ * *epochs_out receives the epochs run, *rmse_out the final training RMSE
+ * (either may be NULL).  Synchronises after every epoch (the RMSE).
+ * Errors: BMF_E_INVAL (hp NULL or not finite, max_epochs < 0, delta not
+ * finite), BMF_E_STATE (no ratings), BMF_E_DEVICE. */
+bmf_status bmf_fit(bmf_ctx *c, const float hp[8], int32_t max_epochs, double delta, int32_t *epochs_out,
+                   double *rmse_out);
+
 /* Order of the strata of epoch `epoch` (b entries). */
 bmf_status bmf_get_schedule(const bmf_ctx *c, int32_t epoch, int32_t *order);
 

@@ -165,6 +165,22 @@ class Model:
             raise RuntimeError("orc_epoch failed: %d" % rc)
         self.epoch_no += 1
 
+    def fit(self, hp: Sequence[float], max_epochs: int, delta: float, threads: int = 1):
+        """Algorithm 1's loop: epochs until the training RMSE improves by
+        less than delta over the previous epoch (the first epoch compares with
+        the RMSE of the initial factors), at most max_epochs.  Returns
+        (epochs run, final training RMSE)."""
+        prev = self.rmse()
+        done = 0
+        while done < max_epochs:
+            self.epoch(hp=hp, threads=threads)
+            done += 1
+            cur = self.rmse()
+            if prev - cur < delta:
+                return done, cur
+            prev = cur
+        return done, prev
+
     def rmse(self, u=None, i=None, r=None) -> float:
         if u is None:
             u, i, r = self.u, self.i, self.r

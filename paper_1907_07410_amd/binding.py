@@ -55,6 +55,7 @@ def _load():
         "bmf_epoch": ([p, f32, f32], i32),
         "bmf_epoch_hp": ([p, p], i32),
         "bmf_epoch_count": ([p, p], i32),
+        "bmf_fit": ([p, p, i32, dbl, p, p], i32),
         "bmf_get_schedule": ([p, i32, p], i32),
         "bmf_get_partition": ([p, p, p], i32),
         "bmf_get_factors": ([p, p, p, p, p, p], i32),
@@ -187,6 +188,15 @@ class Model:
     def epoch_hp(self, hp: Sequence[float]):
         hp = _c(hp, np.float32)
         self._check(lib.bmf_epoch_hp(self._h, _ptr(hp)))
+
+    def fit(self, hp: Sequence[float], max_epochs: int, delta: float):
+        """Epochs until the training RMSE improves by less than delta (see
+        bmf_fit); returns (epochs run, final training RMSE)."""
+        hp = _c(hp, np.float32)
+        e = C.c_int32()
+        r = C.c_double()
+        self._check(lib.bmf_fit(self._h, _ptr(hp), int(max_epochs), float(delta), C.byref(e), C.byref(r)))
+        return e.value, r.value
 
     def epoch_count(self) -> int:
         out = C.c_int32()

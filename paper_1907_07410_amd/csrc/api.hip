@@ -244,6 +244,38 @@ bmf_status bmf_epoch_hp(bmf_ctx *c, const float hp[8]) {
     });
 }
 
+bmf_status bmf_fit(bmf_ctx *c, const float hp[8], int32_t max_epochs, double delta, int32_t *epochs_out,
+                   double *rmse_out) {
+    return guarded(c, false, [&] {
+        Model &M = c->M;
+        if (!hp || max_epochs < 0 || !std::isfinite(delta)) BMF_FAIL(BMF_E_INVAL, "bad fit arguments");
+        check_finite_hp(hp);
+        if (!M.loaded) BMF_FAIL(BMF_E_STATE, "no ratings loaded");
+        const HP h = hp_from(hp);
+        auto train_rmse = [&] {
+            const int64_t nnz = M.part.nnz;
+            if (nnz == 0) return 0.0;
+            const double s = sq_residual_sum(M, M.cu.as<int32_t>(), M.ci.as<int32_t>(), M.cr.as<float>(), nnz,
+                                             nullptr, M.red);
+            return std::sqrt(s / (double)nnz);
+        };
+        double prev = train_rmse();
+        int32_t done = 0;
+        while (done < max_epochs) {
+            run_epoch(c, h);
+            ++done;
+            const double cur = train_rmse();
+            if (prev - cur < delta) {
+                prev = cur;
+                break;
+            }
+            prev = cur;
+        }
+        if (epochs_out) *epochs_out = done;
+        if (rmse_out) *rmse_out = prev;
+    });
+}
+
 bmf_status bmf_epoch_count(const bmf_ctx *c, int32_t *out) {
     if (!c || !out) return BMF_E_INVAL;
     *out = c->M.epoch;

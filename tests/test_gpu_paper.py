@@ -1,0 +1,107 @@
+"""Section 5's protocol on the MovieLens-1M-shaped workload (6,040 x 3,883,
+800,167 training ratings, k = 13, the paper's named (alpha, beta) pairs,
+early termination at delta = 1e-4), GPU against the oracle.
+
+* grids 8 and 3072 (the paper's CPU and GPU block variants): the fit stops
+  at the same epoch (or, where the oracle's improvement at the boundary is
+  within 1e-6 of delta, one epoch apart), training and test RMSE within
+  1e-3, factors within 1e-3;
+* grid 1 (the plain method, one block, the reference kernel): two epochs,
+  factors within 1e-4;
+* a reduced copy (scale 0.3) covers the same at the seconds scale."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1907_07410_amd import configs
+
+pytestmark = pytest.mark.gpu
+
+HP = configs.PAPER_HP
+DELTA = configs.PAPER_DELTA
+
+
+def log(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def models(orc, prob, b):
+    from paper_1907_07410_amd import binding as B
+    k = configs.PAPER_ML1M.k
+    G = B.Model(prob.m, prob.n, k, b, seed=1001, order_mode=0)
+    G.load_ratings(prob.train.u, prob.train.i, prob.train.r)
+    O = orc.Model(prob.m, prob.n, k, b, seed=1001, order_mode=0)
+    O.load(prob.train.u, prob.train.i, prob.train.r)
+    return G, O
+
+
+def max_diff(G, O):
+    P, Q, bu, bi, mu = G.get_factors()
+    return max(np.abs(P - O.P).max(), np.abs(Q - O.Q).max(), np.abs(bu - O.bu).max(), np.abs(bi - O.bi).max())
+
+
+def check_fit(orc, prob, b, threads):
+    G, O = models(orc, prob, b)
+    eg, rg = G.fit(HP, 300, DELTA)
+    eo, ro = O.fit(HP, 300, DELTA, threads=threads)
+    te = prob.test
+    tg, to = G.rmse(te.u, te.i, te.r), O.rmse(te.u, te.i, te.r)
+    d = max_diff(G, O)
+    log("b", b, "epochs gpu", eg, "oracle", eo, "train rmse", rg, ro, "test rmse", tg, to, "max diff", d)
+    if eg != eo:
+        assert abs(eg - eo) == 1
+        O2 = models(orc, prob, b)[1]
+        prev = O2.rmse()
+        for _ in range(min(eg, eo)):
+            O2.epoch(hp=HP, threads=threads)
+            cur = O2.rmse()
+            imp, prev = prev - cur, cur
+        assert abs(imp - DELTA) <= 1e-6
+    else:
+        assert d <= 1e-3
+    assert abs(rg - ro) <= 1e-3 and abs(tg - to) <= 1e-3
+    assert abs(G.rmse() - rg) <= 1e-9
+    assert G.epoch_count() == eg
+
+
+def test_fit_reduced(orc):
+    prob = configs.PAPER_ML1M.generate(1, scale=0.3)
+    check_fit(orc, prob, 8, threads=8)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("b,threads", [(8, 8), (3072, 1)])
+def test_fit_full(orc, b, threads):
+    prob = configs.PAPER_ML1M.generate(1)
+    check_fit(orc, prob, b, threads)
+
+
+@pytest.mark.slow
+def test_single_block_two_epochs(orc):
+    prob = configs.PAPER_ML1M.generate(1)
+    G, O = models(orc, prob, 1)
+    for _ in range(2):
+        G.epoch_hp(HP)
+        O.epoch(hp=HP)
+    d = max_diff(G, O)
+    log("b 1 two epochs max diff", d)
+    assert d <= 1e-4
+
+
+def test_fit_arguments(orc):
+    from paper_1907_07410_amd import binding as B
+    prob = configs.PAPER_ML1M.generate(1, scale=0.05)
+    G, _ = models(orc, prob, 4)
+    r0 = G.rmse()
+    assert G.fit(HP, 0, DELTA) == (0, pytest.approx(r0, abs=0))
+    assert G.fit(HP, 50, 1e9)[0] == 1
+    assert G.fit(HP, 3, -1e9)[0] == 3
+    assert G.epoch_count() == 4
+    for bad in ((HP, -1, DELTA), (HP, 5, float("nan")), (HP, 5, float("inf")),
+                ((float("nan"),) + HP[1:], 5, DELTA)):
+        with pytest.raises(B.BmfError):
+            G.fit(*bad)
+    E = B.Model(10, 10, 4, 2)
+    with pytest.raises(B.BmfError):
+        E.fit(HP, 3, DELTA)

@@ -172,71 +172,88 @@ def batched_leg(binding, args, torch):
 def paper_leg(binding, args):
     """Section 5's protocol on the MovieLens-1M-shaped workload (6,040 x
     3,883, 800,167 training ratings, k = 13, the paper's named pairs, early
-    termination at delta = 1e-4): seconds per iteration and test RMSE at the
-    grids of Table 1's rows, 8 x 8 (BCSVD) and 3072 x 3072 (BGSVD) fitted to
-    the stopping rule, 1 x 1 (plain SVD, one block on the reference kernel)
-    timed over two epochs; the oracle's 8 x 8 fit and 1 x 1 epochs on the host
-    beside them.  The paper's own Table 1 figures (other data, other machines)
-    are attached as context."""
+    termination at delta = 1e-4), over three data seeds as Table 1 does:
+    seconds per iteration and test RMSE at the grids of Table 1's rows, 8 x 8
+    (BCSVD) and 3072 x 3072 (BGSVD) fitted to the stopping rule, 1 x 1 (plain
+    SVD, one block on the reference kernel) timed over two epochs; the
+    oracle's 8 x 8 fit and 1 x 1 epochs on the host beside them.  The
+    paper's own Table 1 figures (other data, other machines) are attached as
+    context."""
     from paper_1907_07410_amd import configs
     c = configs.PAPER_ML1M
-    prob = c.generate(args.seed)
-    tr, te = prob.train, prob.test
-    out = {"workload": "6040 users x 3883 items, %d train / %d test ratings, k=13" % (len(tr), len(te)),
-           "delta": configs.PAPER_DELTA, "hp": list(configs.PAPER_HP), "gpu": {}, "oracle": {},
-           "paper_table1_ml1m_context": {"SVD_s_per_iter": 49.56, "BCSVD_s_per_iter": 34.53,
-                                         "BGSVD_s_per_iter": 13.45, "SVD_test_rmse": 0.867,
-                                         "BCSVD_test_rmse": 0.871, "BGSVD_test_rmse": 0.869,
-                                         "hardware": "Xeon E5-2640 v3 / Tesla M40, MovieLens-1M"}}
-    for b in (8, 3072):
-        G = binding.Model(prob.m, prob.n, c.k, b, seed=args.seed + 1000, order_mode=0)
-        t0 = time.perf_counter()
+    seeds = (args.seed, args.seed + 1, args.seed + 2)
+    runs = {"gpu_b8": [], "gpu_b3072": [], "gpu_b1": [], "oracle_b8": [], "oracle_b1": []}
+    threads = max(1, min(len(os.sched_getaffinity(0)), 8))
+    for seed in seeds:
+        prob = c.generate(seed)
+        tr, te = prob.train, prob.test
+        for b in (8, 3072):
+            G = binding.Model(prob.m, prob.n, c.k, b, seed=seed + 1000, order_mode=0)
+            t0 = time.perf_counter()
+            G.load_ratings(tr.u, tr.i, tr.r)
+            load_s = time.perf_counter() - t0
+            G.epoch_hp([0.0] * 8)  # warm-up launch: zero rates leave the factors as they are
+            G.synchronize()
+            t0 = time.perf_counter()
+            e, r = G.fit(configs.PAPER_HP, 1000, configs.PAPER_DELTA)
+            el = time.perf_counter() - t0
+            runs[f"gpu_b{b}"].append({"seed": seed, "epochs": e, "s_per_iter": el / e, "train_rmse": r,
+                                      "test_rmse": G.rmse(te.u, te.i, te.r), "load_s": load_s})
+            log(f"paper protocol seed {seed} b={b}: {e} epochs, {el / e * 1e3:.2f} ms/iter, test rmse "
+                f"{runs[f'gpu_b{b}'][-1]['test_rmse']:.4f}, load {load_s:.2f}s")
+            del G
+        G = binding.Model(prob.m, prob.n, c.k, 1, seed=seed + 1000, order_mode=0)
         G.load_ratings(tr.u, tr.i, tr.r)
-        load_s = time.perf_counter() - t0
-        G.epoch_hp([0.0] * 8)  # warm-up launch: zero rates leave the factors as they are
         G.synchronize()
         t0 = time.perf_counter()
-        e, r = G.fit(configs.PAPER_HP, 1000, configs.PAPER_DELTA)
-        el = time.perf_counter() - t0
-        out["gpu"][f"b{b}"] = {"epochs": e, "s_per_iter": el / e, "train_rmse": r,
-                               "test_rmse": G.rmse(te.u, te.i, te.r), "load_s": load_s,
-                               "updates_per_s": len(tr) * e / el}
-        log(f"paper protocol b={b}: {e} epochs, {el / e * 1e3:.2f} ms/iter, test rmse "
-            f"{out['gpu'][f'b{b}']['test_rmse']:.4f}, load {load_s:.2f}s")
+        for _ in range(2):
+            G.epoch_hp(configs.PAPER_HP)
+        G.synchronize()
+        runs["gpu_b1"].append({"seed": seed, "epochs_timed": 2, "s_per_iter": (time.perf_counter() - t0) / 2})
         del G
-    G = binding.Model(prob.m, prob.n, c.k, 1, seed=args.seed + 1000, order_mode=0)
-    G.load_ratings(tr.u, tr.i, tr.r)
-    G.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(2):
-        G.epoch_hp(configs.PAPER_HP)
-    G.synchronize()
-    el = (time.perf_counter() - t0) / 2
-    out["gpu"]["b1"] = {"epochs_timed": 2, "s_per_iter": el, "updates_per_s": len(tr) / el,
-                        "note": "one block: a single dependent chain on the reference kernel"}
-    log(f"paper protocol b=1: {el * 1e3:.1f} ms/iter")
-    del G
-    if not args.no_cpu_baseline:
+        if args.no_cpu_baseline:
+            continue
         import oracle
-        threads = max(1, min(len(os.sched_getaffinity(0)), 8))
-        O = oracle.Model(prob.m, prob.n, c.k, 8, seed=args.seed + 1000, order_mode=0)
+        O = oracle.Model(prob.m, prob.n, c.k, 8, seed=seed + 1000, order_mode=0)
         O.load(tr.u, tr.i, tr.r)
         t0 = time.perf_counter()
         e, r = O.fit(configs.PAPER_HP, 1000, configs.PAPER_DELTA, threads=threads)
         el = time.perf_counter() - t0
-        out["oracle"]["b8"] = {"epochs": e, "s_per_iter": el / e, "train_rmse": r,
-                               "test_rmse": O.rmse(te.u, te.i, te.r), "threads": threads}
-        O = oracle.Model(prob.m, prob.n, c.k, 1, seed=args.seed + 1000, order_mode=0)
+        runs["oracle_b8"].append({"seed": seed, "epochs": e, "s_per_iter": el / e, "train_rmse": r,
+                                  "test_rmse": O.rmse(te.u, te.i, te.r), "threads": threads})
+        O = oracle.Model(prob.m, prob.n, c.k, 1, seed=seed + 1000, order_mode=0)
         O.load(tr.u, tr.i, tr.r)
         t0 = time.perf_counter()
         for _ in range(2):
             O.epoch(hp=configs.PAPER_HP)
-        out["oracle"]["b1"] = {"epochs_timed": 2, "s_per_iter": (time.perf_counter() - t0) / 2, "threads": 1}
-        g8, o8 = out["gpu"]["b8"], out["oracle"]["b8"]
-        out["b8_matched"] = bool(abs(g8["epochs"] - o8["epochs"]) <= 1 and
-                                 abs(g8["test_rmse"] - o8["test_rmse"]) <= 1e-3)
-        log(f"paper protocol oracle b=8: {o8['epochs']} epochs, {o8['s_per_iter'] * 1e3:.1f} ms/iter on "
-            f"{threads} threads, test rmse {o8['test_rmse']:.4f}; b=1 {out['oracle']['b1']['s_per_iter'] * 1e3:.1f} ms/iter")
+        runs["oracle_b1"].append({"seed": seed, "epochs_timed": 2, "s_per_iter": (time.perf_counter() - t0) / 2,
+                                  "threads": 1})
+        log(f"paper protocol seed {seed} oracle b=8: {e} epochs, {el / e * 1e3:.1f} ms/iter on {threads} threads, "
+            f"test rmse {runs['oracle_b8'][-1]['test_rmse']:.4f}; b=1 "
+            f"{runs['oracle_b1'][-1]['s_per_iter'] * 1e3:.1f} ms/iter")
+
+    def summary(rows):
+        if not rows:
+            return None
+        out = {"runs": rows}
+        for key in ("s_per_iter", "test_rmse", "epochs"):
+            if key in rows[0]:
+                v = np.array([r[key] for r in rows], dtype=np.float64)
+                out[key + "_mean"] = float(v.mean())
+                out[key + "_sd"] = float(v.std(ddof=1)) if len(v) > 1 else 0.0
+        return out
+
+    out = {"workload": "6040 users x 3883 items, 1,000,209 ratings (80/20 split), k=13, seeds %s" % (seeds,),
+           "delta": configs.PAPER_DELTA, "hp": list(configs.PAPER_HP),
+           "paper_table1_ml1m_context": {"SVD_s_per_iter": 49.56, "BCSVD_s_per_iter": 34.53,
+                                         "BGSVD_s_per_iter": 13.45, "SVD_test_rmse": 0.867,
+                                         "BCSVD_test_rmse": 0.871, "BGSVD_test_rmse": 0.869,
+                                         "hardware": "Xeon E5-2640 v3 / Tesla M40, MovieLens-1M"}}
+    for key, rows in runs.items():
+        out[key] = summary(rows)
+    if runs["oracle_b8"]:
+        out["b8_matched"] = bool(all(abs(g["epochs"] - o["epochs"]) <= 1 and abs(g["test_rmse"] - o["test_rmse"]) <= 1e-3
+                                     for g, o in zip(runs["gpu_b8"], runs["oracle_b8"])))
     return out
 
 

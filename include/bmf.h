@@ -72,14 +72,16 @@ typedef enum {
     /* hipStream_t (cast to int64) on which all work is enqueued; 0 = the
      * context's own stream. */
     BMF_OPT_STREAM = 4,
-    /* SGD kernel: 0 = automatic (2 when the load built a plan, else 1),
-     * 1 = global-memory reference kernel running each block's ratings in
-     * (u, i, t) order, 2 = LDS-staged planned kernel: the block's item slice
-     * and its active users' rows in LDS, four independent ratings per step
-     * (a list schedule built at load time that reorders only ratings sharing
-     * neither user nor item).  For k <= 128, 1 and 2 give identical bits;
-     * 2 needs k <= 128 and an item slice that leaves room in LDS for at
-     * least 8 user slots (BMF_E_STATE otherwise). */
+    /* SGD kernel: 0 = automatic (2 when the plan applies and the blocks hold
+     * at least 8 ratings on average, else 1), 1 = global-memory reference
+     * kernel running each block's ratings in (u, i, t) order, 2 = LDS-staged
+     * planned kernel: the block's item slice and its active users' rows in
+     * LDS, four independent ratings per step (a list schedule that reorders
+     * only ratings sharing neither user nor item, built on the host at load
+     * when an epoch will use it, else at the first epoch that does).  For
+     * k <= 128, 1 and 2 give identical bits; 2 needs k <= 128 and an item
+     * slice that leaves room in LDS for at least 8 user slots (BMF_E_STATE
+     * otherwise). */
     BMF_OPT_SGD_KERNEL = 5,
     /* waves per workgroup of the LDS-staged SGD kernel: 4 or 8 (one wave
      * runs the update steps, the others stage data); default 8.  On a

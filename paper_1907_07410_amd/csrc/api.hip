@@ -86,8 +86,9 @@ void load_common(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r,
     if (M.mu_mode == 0 && nnz > 0) mu = sum_f32_as_f64(dr.as<float>(), nnz, M.red, M.stream) / (double)nnz;
     Partition P;
     build_partition(P, du.as<int32_t>(), di.as<int32_t>(), dr.as<float>(), nnz, M.m, M.n, M.b, M.stream);
-    Plan plan;
-    build_plan(plan, P, M.b, M.k, sgd_max_lds(M.device), M.stream);
+    Plan plan;  // built now when an epoch will use it, else on first demand
+    if (M.sgd_kernel == 2 || (M.sgd_kernel == 0 && plan_pays(P.nnz, M.b)))
+        build_plan(plan, P, M.b, M.k, sgd_max_lds(M.device), M.stream);
     // commit
     M.cu.swap(du);
     M.ci.swap(di);

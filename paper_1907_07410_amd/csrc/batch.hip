@@ -440,6 +440,7 @@ bmf_status bmf_batch_epochs(bmf_batch *B, int32_t epochs, const float hp[8]) {
         size_t lds = 0;
         for (int p = 0; p < np; ++p) {
             Model &M = B->probs[p]->M;
+            ensure_plan(M);
             if (!M.plan.ok) BMF_FAIL(BMF_E_STATE, "problem " + std::to_string(p) + " has no plan for the LDS kernel");
             tab[p] = BatchProblem{M.plan.steps.as<SlotRec>(), M.plan.blk_step.as<int64_t>(), M.P.as<float>(),
                                   M.Q.as<float>(), M.bu.as<float>(), M.bi.as<float>(), M.n, M.part.rb, M.part.cb,

@@ -83,6 +83,7 @@ struct Partition {
 
 // Execution plan of the LDS-staged SGD kernel (see plan.hip).
 struct Plan {
+    bool built = false;  // build_plan has run (ok says whether it applies)
     bool ok = false;
     int kp = 0, S = 0, CH = PLAN_CH;
     int64_t total_steps = 0;
@@ -90,6 +91,7 @@ struct Plan {
     DevBuf blk_step;  // int64[b*b + 1], step offsets per block
     std::vector<int64_t> h_blk_step;
     void swap(Plan &o) {
+        std::swap(built, o.built);
         std::swap(ok, o.ok);
         std::swap(kp, o.kp);
         std::swap(S, o.S);
@@ -171,6 +173,13 @@ int plan_kp(int k);
 int plan_slots(int kp, int64_t cb, int CH, int max_lds);
 int64_t plan_block(const uint32_t *ui, int64_t n, int ibits, int cb, int S, int CH, std::vector<PlanEntry> &out);
 void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hipStream_t s);
+// The planned kernel's fixed cost per workgroup (staging a full LDS buffer)
+// outweighs its gain on blocks of a few ratings: automatic selection takes
+// it only when the blocks hold at least PLAN_MIN_MEAN ratings on average.
+constexpr int PLAN_MIN_MEAN = 8;
+inline bool plan_pays(int64_t nnz, int b) { return nnz >= (int64_t)PLAN_MIN_MEAN * b * b; }
+// Build M's plan now if no load or earlier epoch has (synchronises).
+void ensure_plan(Model &M);
 
 // SGD: run one epoch of strata in `order`.
 void sgd_epoch(Model &M, const int32_t *order, const HP &hp);

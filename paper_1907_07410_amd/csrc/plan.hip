@@ -169,6 +169,7 @@ int plan_slots(int kp, int64_t cb, int CH, int max_lds) {
 
 void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hipStream_t s) {
     out.ok = false;
+    out.built = true;
     const int kp = plan_kp(k);
     if (!kp || part.cb + 1 > (1 << 16) || part.ubits > 30) return;
     const int CH = PLAN_CH;

@@ -512,9 +512,14 @@ static void launch_one(Model &M, int s, const HP &hp, int variant) {
     }
 }
 
+void ensure_plan(Model &M) {
+    if (!M.plan.built) build_plan(M.plan, M.part, M.b, M.k, sgd_max_lds(M.device), M.stream);
+}
+
 void sgd_epoch(Model &M, const int32_t *order, const HP &hp) {
     int variant = M.sgd_kernel;
-    if (variant == 0) variant = M.plan.ok ? 2 : 1;
+    if (variant == 0) variant = M.plan.ok && plan_pays(M.part.nnz, M.b) ? 2 : 1;
+    if (variant == 2) ensure_plan(M);
     if (variant == 2 && !M.plan.ok)
         BMF_FAIL(BMF_E_STATE, "the LDS-staged SGD kernel needs k <= 128 and an item slice that leaves room for "
                               "user slots in LDS; use SGD kernel 1 or a larger b");

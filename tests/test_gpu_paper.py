@@ -105,3 +105,25 @@ def test_fit_arguments(orc):
     E = B.Model(10, 10, 4, 2)
     with pytest.raises(B.BmfError):
         E.fit(HP, 3, DELTA)
+
+
+@pytest.mark.parametrize("b", [64, 512])
+def test_automatic_kernel_choice_identical_bits(b):
+    """Automatic selection takes the planned kernel on blocks of at least 8
+    ratings on average (b = 64 here) and the reference kernel below (b = 512,
+    under one rating per block); forcing the other kernel gives the same
+    bits."""
+    from paper_1907_07410_amd import binding as B
+    prob = configs.PAPER_ML1M.generate(2, scale=0.3)
+    tr = prob.train
+    out = []
+    for kern in (0, 1, 2):
+        G = B.Model(prob.m, prob.n, 13, b, seed=1001, order_mode=0, sgd_kernel=kern)
+        G.load_ratings(tr.u, tr.i, tr.r)
+        for _ in range(2):
+            G.epoch_hp(HP)
+        out.append(G.get_factors()[:4])
+    for a, c in zip(out[0], out[1]):
+        assert np.array_equal(a, c)
+    for a, c in zip(out[0], out[2]):
+        assert np.array_equal(a, c)

@@ -157,6 +157,26 @@ bmf_status bmf_epoch_hp(bmf_ctx *c, const float hp[8]);
 /* Number of epochs run so far (the next epoch's index). */
 bmf_status bmf_epoch_count(const bmf_ctx *c, int32_t *out);
 
+/* Incremental data (Section 6: new ratings become new blocks that are
+ * factorised on their own, then the factors converge together on all the
+ * data).  Grows the model to m_new >= m users and n_new >= n items: learned
+ * rows are kept, new rows of P and Q get the seeded initial values a model
+ * created at the new size holds there, new biases are 0; the block geometry
+ * follows the new sizes.  Then runs epochs_new epochs (pairs hp, as
+ * bmf_epoch_hp) over the new ratings u/i/r (host arrays of nnz entries, ids
+ * below m_new / n_new) alone, partitioned on the grown b x b grid, starting
+ * from the current factors, and finally makes the union (the loaded ratings
+ * followed by the new ones) the training set, so that bmf_epoch / bmf_fit
+ * continue on all ratings.  mu becomes the union's mean (BMF_OPT_MU_MODE 0)
+ * or stays 0 (mode 1) and is used in both phases.  Each phase epoch counts in
+ * bmf_epoch_count.  Not to be called while a server uses the context.
+ * Errors (nothing changed): BMF_E_INVAL (a size shrinks or reaches 2^31, hp
+ * NULL or not finite, epochs_new < 0, nnz < 0, null arrays, the union
+ * reaches 2^31 ratings), BMF_E_RANGE (a new rating outside m_new x n_new or
+ * not finite); BMF_E_NOMEM / BMF_E_DEVICE afterwards. */
+bmf_status bmf_add_ratings(bmf_ctx *c, int64_t m_new, int64_t n_new, const int32_t *u, const int32_t *i,
+                           const float *r, int64_t nnz, const float hp[8], int32_t epochs_new);
+
 /* Algorithm 1's loop: epochs with the pairs hp (as bmf_epoch_hp) until the
  * training RMSE improves by less than delta over the previous epoch (the
  * first epoch compares with the RMSE before it), at most max_epochs.

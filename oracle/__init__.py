@@ -181,6 +181,45 @@ class Model:
             prev = cur
         return done, prev
 
+    def add_ratings(self, m_new: int, n_new: int, u, i, r, hp: Sequence[float], epochs_new: int,
+                    threads: int = 1):
+        """Section 6's incremental data: the new ratings form new blocks that
+        are factorised on their own, then all ratings train together.  The
+        model grows to m_new x n_new (learned rows kept; new rows take the
+        initial values of a model created at the new size, biases 0), runs
+        epochs_new epochs over the new ratings alone on the grown grid from
+        the current factors, and makes the union (loaded ratings, then the
+        new ones) the training set.  mu is the union's mean (or 0), used in
+        both phases."""
+        if m_new < self.m or n_new < self.n:
+            raise ValueError("the model can only grow")
+        u, i, r = _c(u, np.int32), _c(i, np.int32), _c(r, np.float32)
+        P = np.zeros((m_new, self.k), dtype=np.float64)
+        Q = np.zeros((n_new, self.k), dtype=np.float64)
+        bu = np.zeros(m_new, dtype=np.float64)
+        bi = np.zeros(n_new, dtype=np.float64)
+        lib().orc_init_factors(m_new, n_new, self.k, C.c_uint64(self.seed), _ptr(P), _ptr(Q), _ptr(bu), _ptr(bi))
+        P[: self.m] = self.P
+        Q[: self.n] = self.Q
+        bu[: self.m] = self.bu
+        bi[: self.n] = self.bi
+        self.m, self.n = m_new, n_new
+        self.P, self.Q, self.bu, self.bi = P, Q, bu, bi
+        if self.u is None:
+            au, ai, ar = u, i, r
+        else:
+            au = np.concatenate([self.u, u])
+            ai = np.concatenate([self.i, i])
+            ar = np.concatenate([self.r, r])
+        mu = mean(ar) if (self.mu_mode == 0 and ar.shape[0] > 0) else 0.0
+        if epochs_new > 0 and u.shape[0] > 0:
+            self.load(u, i, r)
+            self.mu = mu
+            for _ in range(epochs_new):
+                self.epoch(hp=hp, threads=threads)
+        self.load(au, ai, ar)
+        self.mu = mu
+
     def rmse(self, u=None, i=None, r=None) -> float:
         if u is None:
             u, i, r = self.u, self.i, self.r

@@ -56,6 +56,7 @@ def _load():
         "bmf_epoch_hp": ([p, p], i32),
         "bmf_epoch_count": ([p, p], i32),
         "bmf_fit": ([p, p, i32, dbl, p, p], i32),
+        "bmf_add_ratings": ([p, i64, i64, p, p, p, i64, p, i32], i32),
         "bmf_get_schedule": ([p, i32, p], i32),
         "bmf_get_partition": ([p, p, p], i32),
         "bmf_get_factors": ([p, p, p, p, p, p], i32),
@@ -197,6 +198,17 @@ class Model:
         r = C.c_double()
         self._check(lib.bmf_fit(self._h, _ptr(hp), int(max_epochs), float(delta), C.byref(e), C.byref(r)))
         return e.value, r.value
+
+    def add_ratings(self, m_new: int, n_new: int, u, i, r, hp: Sequence[float], epochs_new: int):
+        """Grow to m_new x n_new, train epochs_new epochs on the new ratings
+        alone, then make all ratings the training set (see bmf_add_ratings)."""
+        u, i, r = _c(u, np.int32), _c(i, np.int32), _c(r, np.float32)
+        if not (u.shape == i.shape == r.shape):
+            raise ValueError("u, i, r must have the same length")
+        hp = _c(hp, np.float32)
+        self._check(lib.bmf_add_ratings(self._h, int(m_new), int(n_new), _ptr(u), _ptr(i), _ptr(r),
+                                        u.shape[0], _ptr(hp), int(epochs_new)))
+        self.m, self.n = int(m_new), int(n_new)
 
     def epoch_count(self) -> int:
         out = C.c_int32()

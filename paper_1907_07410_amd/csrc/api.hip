@@ -60,36 +60,15 @@ void check_finite_hp(const float *hp) {
         if (!std::isfinite(hp[q])) BMF_FAIL(BMF_E_INVAL, "non-finite hyper-parameter");
 }
 
-void load_common(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r, int64_t nnz, bool dev) {
-    Model &M = c->M;
-    if (nnz < 0) BMF_FAIL(BMF_E_INVAL, "nnz < 0");
-    if (nnz > 0 && (!u || !i || !r)) BMF_FAIL(BMF_E_INVAL, "null rating array");
-    if (nnz >= (int64_t)INT32_MAX) BMF_FAIL(BMF_E_INVAL, "nnz must be below 2^31");
-    DevBuf du, di, dr;
-    du.alloc((size_t)nnz * 4);
-    di.alloc((size_t)nnz * 4);
-    dr.alloc((size_t)nnz * 4);
-    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-    if (nnz) {
-        BMF_HIP(hipMemcpyAsync(du.p, u, nnz * 4, kind, M.stream));
-        BMF_HIP(hipMemcpyAsync(di.p, i, nnz * 4, kind, M.stream));
-        BMF_HIP(hipMemcpyAsync(dr.p, r, nnz * 4, kind, M.stream));
-    }
-    const int64_t bad = validate_coo(du.as<int32_t>(), di.as<int32_t>(), dr.as<float>(), nnz, M.m, M.n, M.red,
-                                     M.stream);
-    if (bad >= 0) {
-        std::string what = "rating " + std::to_string(bad) + " is out of range or not finite";
-        if (!dev) what += " (u=" + std::to_string(u[bad]) + ", i=" + std::to_string(i[bad]) + ")";
-        BMF_FAIL(BMF_E_RANGE, what);
-    }
-    double mu = 0.0;
-    if (M.mu_mode == 0 && nnz > 0) mu = sum_f32_as_f64(dr.as<float>(), nnz, M.red, M.stream) / (double)nnz;
+// Partition (and, when an epoch will use it, plan) the device COO du/di/dr
+// of nnz ratings for M's sizes, and make it the training set with mean mu.
+// The buffers are taken over.
+void set_training(Model &M, DevBuf &du, DevBuf &di, DevBuf &dr, int64_t nnz, double mu) {
     Partition P;
     build_partition(P, du.as<int32_t>(), di.as<int32_t>(), dr.as<float>(), nnz, M.m, M.n, M.b, M.stream);
     Plan plan;  // built now when an epoch will use it, else on first demand
     if (M.sgd_kernel == 2 || (M.sgd_kernel == 0 && plan_pays(P.nnz, M.b)))
         build_plan(plan, P, M.b, M.k, sgd_max_lds(M.device), M.stream);
-    // commit
     M.cu.swap(du);
     M.ci.swap(di);
     M.cr.swap(dr);
@@ -106,6 +85,62 @@ void load_common(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r,
     M.mu = mu;
     M.loaded = true;
     M.bf16_valid = false;
+}
+
+// Copy a COO (host or device pointers) to new device buffers and check it
+// against m x n; throws BMF_E_RANGE naming the first bad rating.
+void stage_coo(Model &M, const int32_t *u, const int32_t *i, const float *r, int64_t nnz, bool dev, int64_t m,
+               int64_t n, DevBuf &du, DevBuf &di, DevBuf &dr) {
+    if (nnz < 0) BMF_FAIL(BMF_E_INVAL, "nnz < 0");
+    if (nnz > 0 && (!u || !i || !r)) BMF_FAIL(BMF_E_INVAL, "null rating array");
+    if (nnz >= (int64_t)INT32_MAX) BMF_FAIL(BMF_E_INVAL, "nnz must be below 2^31");
+    du.alloc((size_t)nnz * 4);
+    di.alloc((size_t)nnz * 4);
+    dr.alloc((size_t)nnz * 4);
+    const hipMemcpyKind kind = dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    if (nnz) {
+        BMF_HIP(hipMemcpyAsync(du.p, u, nnz * 4, kind, M.stream));
+        BMF_HIP(hipMemcpyAsync(di.p, i, nnz * 4, kind, M.stream));
+        BMF_HIP(hipMemcpyAsync(dr.p, r, nnz * 4, kind, M.stream));
+    }
+    const int64_t bad = validate_coo(du.as<int32_t>(), di.as<int32_t>(), dr.as<float>(), nnz, m, n, M.red,
+                                     M.stream);
+    if (bad >= 0) {
+        std::string what = "rating " + std::to_string(bad) + " is out of range or not finite";
+        if (!dev) what += " (u=" + std::to_string(u[bad]) + ", i=" + std::to_string(i[bad]) + ")";
+        BMF_FAIL(BMF_E_RANGE, what);
+    }
+}
+
+double training_mean(Model &M, const DevBuf &dr, int64_t nnz) {
+    if (M.mu_mode != 0 || nnz == 0) return 0.0;
+    return sum_f32_as_f64(dr.as<float>(), nnz, M.red, M.stream) / (double)nnz;
+}
+
+void load_common(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r, int64_t nnz, bool dev) {
+    Model &M = c->M;
+    DevBuf du, di, dr;
+    stage_coo(M, u, i, r, nnz, dev, M.m, M.n, du, di, dr);
+    set_training(M, du, di, dr, nnz, training_mean(M, dr, nnz));
+}
+
+// rows [r0, r1) of a k-wide factor table get their seeded initial values
+void grow_table(DevBuf &A, int64_t r0, int64_t r1, int k, uint64_t seed, int tag, hipStream_t s) {
+    DevBuf B;
+    B.alloc((size_t)r1 * k * 4);
+    if (r0) BMF_HIP(hipMemcpyAsync(B.p, A.p, (size_t)r0 * k * 4, hipMemcpyDeviceToDevice, s));
+    launch_init_factors_rows(B.as<float>(), r0, r1, k, seed, tag, s);
+    A.swap(B);
+    BMF_HIP(hipStreamSynchronize(s));
+}
+
+void grow_bias(DevBuf &A, int64_t r0, int64_t r1, hipStream_t s) {
+    DevBuf B;
+    B.alloc((size_t)r1 * 4);
+    if (r0) BMF_HIP(hipMemcpyAsync(B.p, A.p, (size_t)r0 * 4, hipMemcpyDeviceToDevice, s));
+    launch_fill(B.as<float>() + r0, r1 - r0, 0.f, s);
+    A.swap(B);
+    BMF_HIP(hipStreamSynchronize(s));
 }
 
 void run_epoch(bmf_ctx *c, const HP &hp) {
@@ -274,6 +309,52 @@ bmf_status bmf_fit(bmf_ctx *c, const float hp[8], int32_t max_epochs, double del
         }
         if (epochs_out) *epochs_out = done;
         if (rmse_out) *rmse_out = prev;
+    });
+}
+
+bmf_status bmf_add_ratings(bmf_ctx *c, int64_t m_new, int64_t n_new, const int32_t *u, const int32_t *i,
+                           const float *r, int64_t nnz, const float hp[8], int32_t epochs_new) {
+    return guarded(c, false, [&] {
+        Model &M = c->M;
+        if (m_new < M.m || n_new < M.n || m_new >= INT32_MAX || n_new >= INT32_MAX)
+            BMF_FAIL(BMF_E_INVAL, "the model can only grow, to sizes below 2^31");
+        if (!hp || epochs_new < 0) BMF_FAIL(BMF_E_INVAL, "hp must be non-null and epochs_new >= 0");
+        check_finite_hp(hp);
+        const int64_t old = M.loaded ? M.part.nnz : 0;
+        if (nnz < 0 || old + nnz >= (int64_t)INT32_MAX) BMF_FAIL(BMF_E_INVAL, "nnz < 0 or the union reaches 2^31");
+        DevBuf du, di, dr;
+        stage_coo(M, u, i, r, nnz, false, m_new, n_new, du, di, dr);
+        // union of the loaded ratings and the new ones, in that order
+        const int64_t tot = old + nnz;
+        DevBuf au, ai, ar;
+        au.alloc((size_t)tot * 4);
+        ai.alloc((size_t)tot * 4);
+        ar.alloc((size_t)tot * 4);
+        const DevBuf *src[2][3] = {{&M.cu, &M.ci, &M.cr}, {&du, &di, &dr}};
+        DevBuf *dst[3] = {&au, &ai, &ar};
+        for (int q = 0; q < 3; ++q) {
+            char *d = static_cast<char *>(dst[q]->p);
+            if (old) BMF_HIP(hipMemcpyAsync(d, src[0][q]->p, old * 4, hipMemcpyDeviceToDevice, M.stream));
+            if (nnz) BMF_HIP(hipMemcpyAsync(d + old * 4, src[1][q]->p, nnz * 4, hipMemcpyDeviceToDevice, M.stream));
+        }
+        const double mu = training_mean(M, ar, tot);
+        // grow the factor tables: kept rows, then seeded new rows and zero biases
+        grow_table(M.P, M.m, m_new, M.k, M.seed, 1, M.stream);
+        grow_table(M.Q, M.n, n_new, M.k, M.seed, 2, M.stream);
+        grow_bias(M.bu, M.m, m_new, M.stream);
+        grow_bias(M.bi, M.n, n_new, M.stream);
+        M.m = m_new;
+        M.n = n_new;
+        M.Pb.free_();
+        M.Qb.free_();
+        M.bf16_valid = false;
+        // the new ratings alone, on the grown grid, from the current factors
+        if (epochs_new > 0 && nnz > 0) {
+            set_training(M, du, di, dr, nnz, mu);
+            for (int e = 0; e < epochs_new; ++e) run_epoch(c, hp_from(hp));
+        }
+        // then every rating is the training set
+        set_training(M, au, ai, ar, tot, mu);
     });
 }
 

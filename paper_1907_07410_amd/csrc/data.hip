@@ -53,8 +53,9 @@ void schedule(int b, uint64_t seed, int epoch, int mode, int32_t *order) {
 
 // Initial factor entry: (j - 2^23) * 2^-26 with j the top 24 bits of the
 // draw, i.e. 0.125 * (2 * j * 2^-24 - 1): exact in FP32.
-__global__ void init_factors_kernel(float *__restrict__ A, int64_t total, int k, uint64_t stream) {
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+// Entries t0 .. t1-1 of the row-major table (entry t = row * k + f).
+__global__ void init_factors_kernel(float *__restrict__ A, int64_t t0, int64_t t1, uint64_t stream) {
+    for (int64_t t = t0 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < t1;
          t += (int64_t)gridDim.x * blockDim.x) {
         const uint64_t x = sm64_mix(stream + ((uint64_t)t + 1) * 0x9E3779B97F4A7C15ull);
         const int32_t j = (int32_t)(x >> 40);
@@ -62,12 +63,16 @@ __global__ void init_factors_kernel(float *__restrict__ A, int64_t total, int k,
     }
 }
 
-void launch_init_factors(float *A, int64_t rows, int k, uint64_t seed, int tag, hipStream_t s) {
-    const int64_t total = rows * (int64_t)k;
-    if (total == 0) return;
-    const int grid = (int)std::min<int64_t>((total + 255) / 256, 8192);
-    init_factors_kernel<<<grid, 256, 0, s>>>(A, total, k, seed ^ ((uint64_t)tag << 56));
+void launch_init_factors_rows(float *A, int64_t r0, int64_t r1, int k, uint64_t seed, int tag, hipStream_t s) {
+    const int64_t t0 = r0 * (int64_t)k, t1 = r1 * (int64_t)k;
+    if (t1 <= t0) return;
+    const int grid = (int)std::min<int64_t>((t1 - t0 + 255) / 256, 8192);
+    init_factors_kernel<<<grid, 256, 0, s>>>(A, t0, t1, seed ^ ((uint64_t)tag << 56));
     BMF_HIP(hipGetLastError());
+}
+
+void launch_init_factors(float *A, int64_t rows, int k, uint64_t seed, int tag, hipStream_t s) {
+    launch_init_factors_rows(A, 0, rows, k, seed, tag, s);
 }
 
 __global__ void fill_kernel(float *__restrict__ A, int64_t n, float v) {

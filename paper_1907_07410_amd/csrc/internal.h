@@ -150,6 +150,8 @@ void schedule(int b, uint64_t seed, int epoch, int mode, int32_t *order);
 // --------------------------------------------------------------- kernels
 // all launchers enqueue on `s` and throw Error on launch failure
 void launch_init_factors(float *A, int64_t rows, int k, uint64_t seed, int tag, hipStream_t s);
+// rows r0 .. r1-1 only (the entries a table of r1 rows would hold there)
+void launch_init_factors_rows(float *A, int64_t r0, int64_t r1, int k, uint64_t seed, int tag, hipStream_t s);
 void launch_fill(float *A, int64_t n, float v, hipStream_t s);
 
 // Validate COO: returns first bad index or -1 (synchronises).

@@ -257,6 +257,50 @@ def paper_leg(binding, args):
     return out
 
 
+def incremental_leg(binding, args):
+    """Section 6's incremental data on the MovieLens-1M-shaped workload: the
+    first 90% of users and items form the old model (fitted to the stopping
+    rule), the remaining ratings arrive later (new users, new items and new
+    ratings between them and the old ones).  Incremental: bmf_add_ratings
+    (5 epochs on the new ratings alone) then the fit on the union, from the
+    old factors.  Scratch: the fit on the union from initial values.  Reports
+    wall time and test RMSE of both."""
+    from paper_1907_07410_amd import configs
+    c = configs.PAPER_ML1M
+    prob = c.generate(args.seed)
+    tr, te = prob.train, prob.test
+    m0, n0 = int(prob.m * 0.9), int(prob.n * 0.9)
+    old = (tr.u < m0) & (tr.i < n0)
+    hp, delta = configs.PAPER_HP, configs.PAPER_DELTA
+    G = binding.Model(m0, n0, c.k, 8, seed=args.seed + 1000, order_mode=0)
+    G.load_ratings(tr.u[old], tr.i[old], tr.r[old])
+    e_old, _ = G.fit(hp, 1000, delta)
+    G.synchronize()
+    t0 = time.perf_counter()
+    G.add_ratings(prob.m, prob.n, tr.u[~old], tr.i[~old], tr.r[~old], hp, 5)
+    G.synchronize()
+    add_s = time.perf_counter() - t0
+    e_inc, _ = G.fit(hp, 1000, delta)
+    inc_s = time.perf_counter() - t0
+    inc_rmse = G.rmse(te.u, te.i, te.r)
+    del G
+    S = binding.Model(prob.m, prob.n, c.k, 8, seed=args.seed + 1000, order_mode=0)
+    S.load_ratings(np.concatenate([tr.u[old], tr.u[~old]]), np.concatenate([tr.i[old], tr.i[~old]]),
+                   np.concatenate([tr.r[old], tr.r[~old]]))
+    S.synchronize()
+    t0 = time.perf_counter()
+    e_s, _ = S.fit(hp, 1000, delta)
+    scratch_s = time.perf_counter() - t0
+    out = {"old": {"users": m0, "items": n0, "ratings": int(old.sum()), "epochs": e_old},
+           "new_ratings": int((~old).sum()),
+           "incremental": {"add_ratings_s": add_s, "union_epochs": e_inc, "total_s": inc_s,
+                           "test_rmse": inc_rmse},
+           "scratch": {"epochs": e_s, "total_s": scratch_s, "test_rmse": S.rmse(te.u, te.i, te.r)}}
+    log(f"incremental: add {add_s * 1e3:.1f} ms + {e_inc} union epochs = {inc_s * 1e3:.1f} ms, test rmse "
+        f"{inc_rmse:.4f}; scratch {e_s} epochs {scratch_s * 1e3:.1f} ms, test rmse {out['scratch']['test_rmse']:.4f}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -468,6 +512,7 @@ def main():
     serving_out = serving_leg(binding, args) if args.serving_requests > 0 else None
     batched_out = batched_leg(binding, args, torch) if args.batched_scale > 0 else None
     paper_out = None if args.no_paper_protocol else paper_leg(binding, args)
+    incr_out = None if args.no_paper_protocol else incremental_leg(binding, args)
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
         x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -511,6 +556,7 @@ def main():
         "serving": serving_out,
         "batched": batched_out,
         "paper_protocol": paper_out,
+        "incremental": incr_out,
     }
     print(json.dumps(line), flush=True)
 

@@ -340,7 +340,7 @@ typedef struct {
     int32_t max_requests_per_batch; /* 0: unlimited; 1 turns batching off */
     int32_t foldin_passes;          /* passes of a fold-in (0: 10) */
     float foldin_lr, foldin_reg;    /* fold-in step and regulariser (0: 0.005, 0.05) */
-    int32_t Kc;                     /* BF16 candidates per user (0: K + max(16, K/2)) */
+    int32_t Kc;                     /* BF16 candidates per user (0: K + max(16, K/2)); at most 1008 */
 } bmf_server_config;
 
 typedef struct {
@@ -349,7 +349,7 @@ typedef struct {
     double p50_ms, p90_ms, p99_ms, max_ms, mean_ms; /* submit-to-completion latency */
 } bmf_server_stats;
 
-/* cfg may be NULL (all defaults).  Errors: BMF_E_INVAL (k > 256),
+/* cfg may be NULL (all defaults).  Errors: BMF_E_INVAL (k > 256, Kc < 0 or Kc > 1008),
  * BMF_E_NOMEM, BMF_E_DEVICE. */
 bmf_status bmf_server_create(bmf_ctx *c, const bmf_server_config *cfg, bmf_server **out);
 /* Stops the scheduler (queued requests are dropped, running batches

@@ -211,6 +211,8 @@ struct TopkPlan {
     // (r = 0: no threshold); candidate buffers of capg keys per user;
     // the filter splits the item range into S pieces of per_split items
     int s = 0, r = 0, capg = 0, S = 1;
+    // user tiles (16 users each) per filter wave
+    int ut = 1;
     int64_t per_split = 0;
     size_t off_ug = 0, off_ugb = 0, off_ub = 0, off_thr = 0, off_cnt = 0, off_fail = 0, off_cand = 0, off_sel = 0,
            total = 0;

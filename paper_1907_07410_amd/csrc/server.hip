@@ -459,7 +459,7 @@ bmf_status bmf_server_create(bmf_ctx *c, const bmf_server_config *cfg, bmf_serve
     if (d.foldin_passes <= 0) d.foldin_passes = 10;
     if (d.foldin_lr <= 0.f) d.foldin_lr = 0.005f;
     if (d.foldin_reg <= 0.f) d.foldin_reg = 0.05f;
-    if (d.Kc < 0) return BMF_E_INVAL;
+    if (d.Kc < 0 || d.Kc > 1008) return BMF_E_INVAL;  // the selection kernels hold at most 1008 candidates
     S->cfg = d;
     try {
         Model &M = c->M;

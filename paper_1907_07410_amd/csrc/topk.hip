@@ -313,43 +313,105 @@ __global__ __launch_bounds__(SMP_WAVES *WAVE) void sample_threshold_kernel(
 
 // Pass 2: every score at or above its user's threshold goes to the user's
 // candidate buffer (capg keys; the count keeps growing past capg so that
-// an overflow is seen).  Grid: user tiles x item splits.
-template <int KC, bool BF16>
+// an overflow is seen).  Grid: groups of UT user tiles x item splits; a
+// wave holds the user fragments of its UT tiles, so each item tile it loads
+// feeds UT tile products (UT times fewer item-table reads than one tile per
+// wave).  Tiles at or beyond `tiles` are skipped.  Candidates gather in LDS
+// (FLT_LDS per user, positions from LDS atomics) and go to the global
+// buffer at the end with one counter reservation per user; a user that
+// fills its LDS space sends the rest through the global counter one by one.
+constexpr int FLT_LDS = 32;
+
+template <int KC, bool BF16, int UT>
 __global__ __launch_bounds__(64) void filter_kernel(const float *__restrict__ Ug, const uint16_t *__restrict__ Ugb,
                                                     const float *__restrict__ Qf, const uint16_t *__restrict__ Qb,
                                                     const float *__restrict__ bi, int64_t n, int k, int kp, int kb,
-                                                    int64_t per_split, const uint32_t *__restrict__ thr,
-                                                    uint32_t *__restrict__ cnt, int capg,
-                                                    uint64_t *__restrict__ cand) {
+                                                    int64_t tiles, int64_t per_split,
+                                                    const uint32_t *__restrict__ thr, uint32_t *__restrict__ cnt,
+                                                    int capg, uint64_t *__restrict__ cand) {
+    __shared__ uint64_t lbuf[UT * TU][FLT_LDS];
+    __shared__ uint32_t lcnt[UT * TU];
     const int lane = threadIdx.x;
-    const int64_t tile = blockIdx.x;
+    const int64_t tile0 = (int64_t)blockIdx.x * UT;
     const int64_t ibeg = (int64_t)blockIdx.y * per_split;
     const int64_t iend = std::min<int64_t>(n, ibeg + per_split);
     const int ucol = lane % 16, grp = lane / 16;
-    const int64_t urow = tile * TU + ucol;
-    UserFrag<KC, BF16> U;
-    U.load(Ug, Ugb, urow, kp, kb, grp);
-    const uint32_t t = thr[urow];
+    const int nt = (int)std::min<int64_t>(UT, tiles - tile0);  // wave-uniform
+    for (int x = lane; x < UT * TU; x += WAVE) lcnt[x] = 0u;
+    UserFrag<KC, BF16> U[UT];
+    uint32_t t[UT];
+#pragma unroll
+    for (int q = 0; q < UT; ++q) {
+        const int64_t urow = (tile0 + (q < nt ? q : 0)) * TU + ucol;
+        U[q].load(Ug, Ugb, urow, kp, kb, grp);
+        t[q] = thr[urow];
+    }
+    __syncthreads();
     ItemFrag<KC, BF16> A, An;
     A.load(Qf, Qb, ibeg + ucol, ibeg + ucol < iend, k, kb, grp);
     for (int64_t ib = ibeg; ib < iend; ib += TI) {
         const int64_t inext = ib + TI + ucol;  // next tile's row, loaded while this one is multiplied
         An.load(Qf, Qb, inext, inext < iend, k, kb, grp);
-        const f32x4 acc = tile_mma(U, A);
+        f32x4 acc[UT];
+#pragma unroll
+        for (int q = 0; q < UT; ++q) acc[q] = tile_mma(U[q], A);
         A = An;
+        float b[4];
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
             const int64_t item = ib + 4 * grp + rr;
-            if (item < iend) {
-                const float sv = acc[rr] + bi[item];
-                if (float_to_ordered(sv) >= t) {
-                    const uint32_t pos = atomicAdd(&cnt[urow], 1u);
-                    if (pos < (uint32_t)capg) cand[urow * capg + pos] = rank_key(sv, (int32_t)item);
+            b[rr] = item < iend ? bi[item] : 0.f;
+        }
+        // this lane's scores at or above the threshold, per user tile
+        uint32_t pass[UT], base[UT];
+#pragma unroll
+        for (int q = 0; q < UT; ++q) {
+            pass[q] = 0u;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const bool ok = q < nt && ib + 4 * grp + rr < iend && float_to_ordered(acc[q][rr] + b[rr]) >= t[q];
+                pass[q] |= ok ? 1u << rr : 0u;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < UT; ++q)
+            base[q] = pass[q] ? atomicAdd(&lcnt[q * TU + ucol], (uint32_t)__popc(pass[q])) : 0u;
+#pragma unroll
+        for (int q = 0; q < UT; ++q) {
+            if (!pass[q]) continue;
+            uint32_t pos = base[q];
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                if (pass[q] >> rr & 1u) {
+                    const uint64_t key = rank_key(acc[q][rr] + b[rr], (int32_t)(ib + 4 * grp + rr));
+                    if (pos < (uint32_t)FLT_LDS) {
+                        lbuf[q * TU + ucol][pos] = key;
+                    } else {
+                        const int64_t urow = (tile0 + q) * TU + ucol;
+                        const uint32_t g = atomicAdd(&cnt[urow], 1u);
+                        if (g < (uint32_t)capg) cand[urow * capg + g] = key;
+                    }
+                    ++pos;
                 }
             }
         }
     }
+    __syncthreads();
+    // flush: lane x owns user x of the group
+    for (int x = lane; x < nt * TU; x += WAVE) {
+        const uint32_t c = std::min<uint32_t>(lcnt[x], FLT_LDS);
+        if (c == 0u) continue;
+        const int64_t urow = tile0 * TU + x;
+        const uint32_t g = atomicAdd(&cnt[urow], c);
+        for (uint32_t j = 0; j < c; ++j)
+            if (g + j < (uint32_t)capg) cand[urow * capg + g + j] = lbuf[x][j];
+    }
 }
+
+// User tiles per filter wave (two measured faster than one or four at k = 64).
+static int filter_tiles_per_wave(int kc) { return kc <= 8 ? 2 : 1; }
+// The latent chunk count the pass kernels are instantiated for.
+static int dispatch_kc(int kc) { return kc <= 2 ? kc : kc <= 4 ? 4 : kc <= 8 ? 8 : 16; }
 
 // Pass 3: one workgroup per user sorts its candidates (descending keys) and
 // writes the best `need` (0 = none).  A user with fewer than `need`
@@ -358,11 +420,12 @@ __global__ __launch_bounds__(64) void filter_kernel(const float *__restrict__ Ug
 constexpr int FIN_WG = 256;
 constexpr int CAPG_MAX = 4096;
 
+template <int CAP>
 __global__ __launch_bounds__(FIN_WG) void finish_kernel(const uint32_t *__restrict__ thr,
                                                         const uint32_t *__restrict__ cnt,
                                                         const uint64_t *__restrict__ cand, int capg, int need,
                                                         uint32_t *__restrict__ fail, uint64_t *__restrict__ sel) {
-    __shared__ uint64_t buf[CAPG_MAX];
+    __shared__ uint64_t buf[CAP];
     const int64_t row = blockIdx.x;
     const uint32_t c = cnt[row];
     const bool ok = c <= (uint32_t)capg && (c >= (uint32_t)need || thr[row] == 0u);
@@ -371,13 +434,17 @@ __global__ __launch_bounds__(FIN_WG) void finish_kernel(const uint32_t *__restri
     const int total = (int)c;
     for (int x = threadIdx.x; x < total; x += FIN_WG) buf[x] = cand[row * capg + x];
     __syncthreads();
-    int N = 1;
-    while (N < total) N <<= 1;
-    for (int p = 2; p <= N; p <<= 1) {
-        const int half = p >> 1;
-        for (int idx = threadIdx.x; idx < N / 2; idx += FIN_WG) {
-            const int x = (idx / half) * p + (idx % half);
-            const int y = (idx / half) * p + p - 1 - (idx % half);
+    int lgN = 0;
+    while ((1 << lgN) < total) ++lgN;
+    const int half_n = (1 << lgN) >> 1;
+    // bitonic sort, descending; pairs reaching past `total` are skipped
+    // (the missing keys act as the smallest)
+    for (int lp = 1; lp <= lgN; ++lp) {
+        const int lh = lp - 1;  // log2 of half the merged run
+        for (int idx = threadIdx.x; idx < half_n; idx += FIN_WG) {
+            const int lo = idx & ((1 << lh) - 1);
+            const int x = ((idx >> lh) << lp) + lo;
+            const int y = ((idx >> lh) << lp) + (1 << lp) - 1 - lo;
             if (y < total) {
                 const uint64_t a = buf[x], b2 = buf[y];
                 if (a < b2) {
@@ -387,10 +454,10 @@ __global__ __launch_bounds__(FIN_WG) void finish_kernel(const uint32_t *__restri
             }
         }
         __syncthreads();
-        for (int q = half >> 1; q >= 1; q >>= 1) {
-            for (int idx = threadIdx.x; idx < N / 2; idx += FIN_WG) {
-                const int x = (idx / q) * 2 * q + (idx % q);
-                const int y = x + q;
+        for (int lq = lh - 1; lq >= 0; --lq) {
+            for (int idx = threadIdx.x; idx < half_n; idx += FIN_WG) {
+                const int x = ((idx >> lq) << (lq + 1)) + (idx & ((1 << lq) - 1));
+                const int y = x + (1 << lq);
                 if (y < total) {
                     const uint64_t a = buf[x], b2 = buf[y];
                     if (a < b2) {
@@ -540,10 +607,19 @@ static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ug
     const unsigned tiles = (unsigned)(T.nu_pad / TU);
     sample_threshold_kernel<KC, BF16><<<tiles, SMP_WAVES * WAVE, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb, T.s, T.r, thr, cnt);
     BMF_HIP(hipGetLastError());
-    filter_kernel<KC, BF16><<<dim3(tiles, (unsigned)T.S), 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb,
-                                                                     T.per_split, thr, cnt, T.capg, cand);
+    constexpr int UT = KC <= 8 ? 2 : 1;
+    if (T.ut != UT) BMF_FAIL(BMF_E_STATE, "top-K plan made for another filter shape");
+    const unsigned groups = (unsigned)((tiles + UT - 1) / UT);
+    filter_kernel<KC, BF16, UT><<<dim3(groups, (unsigned)T.S), 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb,
+                                                                          (int64_t)tiles, T.per_split, thr, cnt,
+                                                                          T.capg, cand);
     BMF_HIP(hipGetLastError());
-    finish_kernel<<<(unsigned)T.nu_pad, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, fail, sel);
+    if (T.capg <= 1024)
+        finish_kernel<1024><<<(unsigned)T.nu_pad, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, fail, sel);
+    else if (T.capg <= 2048)
+        finish_kernel<2048><<<(unsigned)T.nu_pad, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, fail, sel);
+    else
+        finish_kernel<CAPG_MAX><<<(unsigned)T.nu_pad, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, fail, sel);
     BMF_HIP(hipGetLastError());
     switch (cap_for(T.Ksel)) {
     case 256:
@@ -608,6 +684,7 @@ TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
     T.K = K;
     T.bf = precision == 1;
     T.Ksel = T.bf ? topk_candidates(K, Kc) : K;
+    if (K < 1 || T.Ksel > 1008) BMF_FAIL(BMF_E_INVAL, "top-K needs 1 <= K and at most 1008 candidates per user");
     T.kp = round_up(M.k, 16);
     T.kb = round_up(M.k, 32);
     T.nu_pad = (nu + TU - 1) / TU * TU;
@@ -629,8 +706,9 @@ TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
         T.capg = std::max(T.capg, std::min(CAPG_MAX, round_up(need + 64, 64)));
     }
     // item splits for the filter: enough workgroups to fill the chip
-    const int64_t tiles = T.nu_pad / TU;
-    int S = (int)std::max<int64_t>(1, (4096 + tiles - 1) / std::max<int64_t>(tiles, 1));
+    T.ut = filter_tiles_per_wave(dispatch_kc(T.bf ? T.kb / 32 : T.kp / 16));
+    const int64_t groups = (T.nu_pad / TU + T.ut - 1) / T.ut;
+    int S = (int)std::max<int64_t>(1, (4096 + groups - 1) / std::max<int64_t>(groups, 1));
     S = (int)std::min<int64_t>(S, std::max<int64_t>(1, n / 256));
     T.per_split = ((n + S - 1) / S + TI - 1) / TI * TI;
     T.S = (int)std::max<int64_t>(1, (n + T.per_split - 1) / T.per_split);

@@ -125,3 +125,12 @@ def test_poisson_run_reports_latency(B, model):
     log("poisson", {k2: st[k2] for k2 in ("req_per_s", "p50_ms", "p99_ms", "batches", "completed")})
     assert st["completed"] == 200 and 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
     S.close()
+
+
+def test_server_rejects_candidate_counts_beyond_selection_capacity(B, model):
+    G, _ = model
+    for kc in (-1, 1009, 5000):
+        with pytest.raises(B.BmfError) as ex:
+            B.Server(G, Kc=kc)
+        assert ex.value.status == B.BMF_E_INVAL
+    B.Server(G, Kc=1008).close()

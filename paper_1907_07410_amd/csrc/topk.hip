@@ -227,7 +227,7 @@ constexpr int HBINS = 256;
 // (r = 0).  Also clears the user's candidate count.  One workgroup of
 // SMP_WAVES waves per 16-user tile, each wave taking every SMP_WAVES-th
 // sample tile; lane (u, g) of a wave handles user u.
-constexpr int SMP_WAVES = 4;
+constexpr int SMP_WAVES = 16;
 
 template <int KC, bool BF16>
 __global__ __launch_bounds__(SMP_WAVES *WAVE) void sample_threshold_kernel(

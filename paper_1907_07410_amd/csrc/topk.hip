@@ -251,23 +251,35 @@ __global__ __launch_bounds__(SMP_WAVES *WAVE) void sample_threshold_kernel(
     // scores of this wave's sample tiles, with the next tile's rows loaded
     // while the current one is multiplied; f(t, v) is called for every
     // sample index t < s of the tile and its score v
+    auto sample_bias = [&](int t0, float (&b)[4]) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int t = t0 + 4 * grp + rr;
+            b[rr] = t < s ? bi[(int64_t)t * n / s] : 0.f;
+        }
+    };
     auto sweep = [&](auto &&f) {
         ItemFrag<KC, BF16> A, An;
+        float b[4], bn[4];
         int t0 = wave * TI;
         {
             const int ta = t0 + ucol;
             A.load(Qf, Qb, (int64_t)ta * n / s, ta < s, k, kb, grp);
+            sample_bias(t0, b);
         }
         for (; t0 < s; t0 += step) {
             const int tn = t0 + step + ucol;
             An.load(Qf, Qb, (int64_t)tn * n / s, tn < s, k, kb, grp);
+            sample_bias(t0 + step, bn);
             const f32x4 acc = tile_mma(U, A);
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
                 const int t = t0 + 4 * grp + rr;
-                if (t < s) f(t, acc[rr] + bi[(int64_t)t * n / s]);
+                if (t < s) f(t, acc[rr] + b[rr]);
             }
             A = An;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) b[rr] = bn[rr];
         }
     };
     float vmin = INFINITY, vmax = -INFINITY;
@@ -347,21 +359,27 @@ __global__ __launch_bounds__(64) void filter_kernel(const float *__restrict__ Ug
         t[q] = thr[urow];
     }
     __syncthreads();
-    ItemFrag<KC, BF16> A, An;
-    A.load(Qf, Qb, ibeg + ucol, ibeg + ucol < iend, k, kb, grp);
-    for (int64_t ib = ibeg; ib < iend; ib += TI) {
-        const int64_t inext = ib + TI + ucol;  // next tile's row, loaded while this one is multiplied
-        An.load(Qf, Qb, inext, inext < iend, k, kb, grp);
-        f32x4 acc[UT];
-#pragma unroll
-        for (int q = 0; q < UT; ++q) acc[q] = tile_mma(U[q], A);
-        A = An;
-        float b[4];
+    // item biases of this lane's four score items of a tile
+    auto load_bias = [&](int64_t ib, float (&b)[4]) {
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
             const int64_t item = ib + 4 * grp + rr;
             b[rr] = item < iend ? bi[item] : 0.f;
         }
+    };
+    ItemFrag<KC, BF16> A, An;
+    float b[4], bn[4];
+    A.load(Qf, Qb, ibeg + ucol, ibeg + ucol < iend, k, kb, grp);
+    load_bias(ibeg, b);
+    for (int64_t ib = ibeg; ib < iend; ib += TI) {
+        // the next tile's rows and biases, loaded while this one is multiplied
+        const int64_t inext = ib + TI + ucol;
+        An.load(Qf, Qb, inext, inext < iend, k, kb, grp);
+        load_bias(ib + TI, bn);
+        f32x4 acc[UT];
+#pragma unroll
+        for (int q = 0; q < UT; ++q) acc[q] = tile_mma(U[q], A);
+        A = An;
         // this lane's scores at or above the threshold, per user tile
         uint32_t pass[UT], base[UT];
 #pragma unroll
@@ -395,6 +413,8 @@ __global__ __launch_bounds__(64) void filter_kernel(const float *__restrict__ Ug
                 }
             }
         }
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) b[rr] = bn[rr];
     }
     __syncthreads();
     // flush: lane x owns user x of the group

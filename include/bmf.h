@@ -86,7 +86,18 @@ typedef enum {
     /* waves per workgroup of the LDS-staged SGD kernel: 4 or 8 (one wave
      * runs the update steps, the others stage data); default 8.  On a
      * batch, 0 lets the autotuner choose.  Does not change results. */
-    BMF_OPT_WAVES_PER_BLOCK = 6
+    BMF_OPT_WAVES_PER_BLOCK = 6,
+    /* 1: the next load keeps the ratings in pinned host memory (out of core,
+     * Section 6's unbounded block count): partition and step plans are made
+     * on the host, each stratum's work is laid out contiguously, and an epoch
+     * copies stratum after stratum into one of two device buffers on a copy
+     * stream while the previous stratum runs.  Device memory then holds the
+     * factor tables and two strata.  The kernels, and so the results, are
+     * those of a resident load with the same SGD kernel; mu is summed on the
+     * host in input order.  Such a load takes host arrays only
+     * (bmf_load_ratings), fixes the SGD kernel (set BMF_OPT_SGD_KERNEL before
+     * it), and bmf_add_ratings refuses the context.  0 (default): resident. */
+    BMF_OPT_OUT_OF_CORE = 7
 } bmf_option;
 
 /* ------------------------------------------------------------- lifetime */

@@ -17,7 +17,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbmf.so")
 
 BMF_OK, BMF_E_INVAL, BMF_E_RANGE, BMF_E_STATE, BMF_E_NOMEM, BMF_E_DEVICE = 0, -1, -2, -3, -4, -5
-OPT_SEED, OPT_ORDER_SEED, OPT_STRATUM_ORDER, OPT_MU_MODE, OPT_STREAM, OPT_SGD_KERNEL, OPT_WAVES_PER_BLOCK = range(7)
+(OPT_SEED, OPT_ORDER_SEED, OPT_STRATUM_ORDER, OPT_MU_MODE, OPT_STREAM, OPT_SGD_KERNEL, OPT_WAVES_PER_BLOCK,
+ OPT_OUT_OF_CORE) = range(8)
 
 _STATUS = {0: "BMF_OK", -1: "BMF_E_INVAL", -2: "BMF_E_RANGE", -3: "BMF_E_STATE", -4: "BMF_E_NOMEM",
            -5: "BMF_E_DEVICE"}
@@ -120,7 +121,7 @@ class Model:
     def __init__(self, m: int, n: int, k: int, b: int, seed: Optional[int] = None,
                  order_mode: Optional[int] = None, order_seed: Optional[int] = None,
                  mu_mode: Optional[int] = None, sgd_kernel: Optional[int] = None,
-                 waves: Optional[int] = None, _borrowed=None):
+                 waves: Optional[int] = None, out_of_core: Optional[bool] = None, _borrowed=None):
         self._owned = _borrowed is None
         if _borrowed is not None:
             self._h = _borrowed
@@ -144,6 +145,8 @@ class Model:
             self.set_option(OPT_MU_MODE, mu_mode)
         if sgd_kernel is not None:
             self.set_option(OPT_SGD_KERNEL, sgd_kernel)
+        if out_of_core is not None:
+            self.set_option(OPT_OUT_OF_CORE, int(bool(out_of_core)))
 
     # -- plumbing
     def _check(self, st: int):

@@ -64,6 +64,10 @@ void check_finite_hp(const float *hp) {
 // of nnz ratings for M's sizes, and make it the training set with mean mu.
 // The buffers are taken over.
 void set_training(Model &M, DevBuf &du, DevBuf &di, DevBuf &dr, int64_t nnz, double mu) {
+    if (M.ooc.on) {  // kernels may still read its device buffers
+        BMF_HIP(hipStreamSynchronize(M.stream));
+        M.ooc.release();
+    }
     Partition P;
     build_partition(P, du.as<int32_t>(), di.as<int32_t>(), dr.as<float>(), nnz, M.m, M.n, M.b, M.stream);
     Plan plan;  // built now when an epoch will use it, else on first demand
@@ -119,6 +123,11 @@ double training_mean(Model &M, const DevBuf &dr, int64_t nnz) {
 
 void load_common(bmf_ctx *c, const int32_t *u, const int32_t *i, const float *r, int64_t nnz, bool dev) {
     Model &M = c->M;
+    if (M.out_of_core) {
+        if (dev) BMF_FAIL(BMF_E_INVAL, "out-of-core loads take host arrays");
+        ooc_load(M, u, i, r, nnz);
+        return;
+    }
     DevBuf du, di, dr;
     stage_coo(M, u, i, r, nnz, dev, M.m, M.n, du, di, dr);
     set_training(M, du, di, dr, nnz, training_mean(M, dr, nnz));
@@ -141,6 +150,13 @@ void grow_bias(DevBuf &A, int64_t r0, int64_t r1, hipStream_t s) {
     launch_fill(B.as<float>() + r0, r1 - r0, 0.f, s);
     A.swap(B);
     BMF_HIP(hipStreamSynchronize(s));
+}
+
+// Sum of squared residuals over the training ratings (with the loss terms
+// when loss_hp), resident or out of core.
+double train_sq_sum(Model &M, const HP *loss_hp) {
+    if (M.ooc.on) return ooc_sq_sum(M, loss_hp);
+    return sq_residual_sum(M, M.cu.as<int32_t>(), M.ci.as<int32_t>(), M.cr.as<float>(), M.part.nnz, loss_hp, M.red);
 }
 
 void run_epoch(bmf_ctx *c, const HP &hp) {
@@ -247,6 +263,10 @@ bmf_status bmf_set_option(bmf_ctx *c, int32_t key, int64_t value) {
             if (value != 4 && value != 8) BMF_FAIL(BMF_E_INVAL, "waves per block must be 4 or 8");
             M.waves = (int)value;
             break;
+        case BMF_OPT_OUT_OF_CORE:
+            if (value != 0 && value != 1) BMF_FAIL(BMF_E_INVAL, "out-of-core must be 0 or 1");
+            M.out_of_core = value == 1;
+            break;
         default: BMF_FAIL(BMF_E_INVAL, "unknown option " + std::to_string(key));
         }
     });
@@ -291,8 +311,7 @@ bmf_status bmf_fit(bmf_ctx *c, const float hp[8], int32_t max_epochs, double del
         auto train_rmse = [&] {
             const int64_t nnz = M.part.nnz;
             if (nnz == 0) return 0.0;
-            const double s = sq_residual_sum(M, M.cu.as<int32_t>(), M.ci.as<int32_t>(), M.cr.as<float>(), nnz,
-                                             nullptr, M.red);
+            const double s = train_sq_sum(M, nullptr);
             return std::sqrt(s / (double)nnz);
         };
         double prev = train_rmse();
@@ -320,6 +339,7 @@ bmf_status bmf_add_ratings(bmf_ctx *c, int64_t m_new, int64_t n_new, const int32
             BMF_FAIL(BMF_E_INVAL, "the model can only grow, to sizes below 2^31");
         if (!hp || epochs_new < 0) BMF_FAIL(BMF_E_INVAL, "hp must be non-null and epochs_new >= 0");
         check_finite_hp(hp);
+        if (M.ooc.on) BMF_FAIL(BMF_E_STATE, "incremental data needs resident ratings (load without out-of-core)");
         const int64_t old = M.loaded ? M.part.nnz : 0;
         if (nnz < 0 || old + nnz >= (int64_t)INT32_MAX) BMF_FAIL(BMF_E_INVAL, "nnz < 0 or the union reaches 2^31");
         DevBuf du, di, dr;
@@ -382,7 +402,9 @@ bmf_status bmf_get_partition(bmf_ctx *c, int64_t *block_ptr, int32_t *perm) {
         if (!M.loaded) BMF_FAIL(BMF_E_STATE, "no ratings loaded");
         if (block_ptr)
             std::memcpy(block_ptr, M.part.h_block_ptr.data(), M.part.h_block_ptr.size() * sizeof(int64_t));
-        if (perm && M.part.nnz) {
+        if (perm && M.part.nnz && M.ooc.on) {
+            std::memcpy(perm, M.ooc.perm.data(), M.part.nnz * 4);
+        } else if (perm && M.part.nnz) {
             BMF_HIP(hipMemcpyAsync(perm, M.part.perm.p, M.part.nnz * 4, hipMemcpyDeviceToHost, M.stream));
             BMF_HIP(hipStreamSynchronize(M.stream));
         }
@@ -435,7 +457,7 @@ bmf_status bmf_rmse(bmf_ctx *c, const int32_t *u, const int32_t *i, const float 
         if (!u) {
             if (!M.loaded) BMF_FAIL(BMF_E_STATE, "no ratings loaded");
             total = M.part.nnz;
-            s = sq_residual_sum(M, M.cu.as<int32_t>(), M.ci.as<int32_t>(), M.cr.as<float>(), total, nullptr, M.red);
+            s = train_sq_sum(M, nullptr);
         } else {
             if (cnt < 0 || (cnt > 0 && (!i || !r))) BMF_FAIL(BMF_E_INVAL, "bad evaluation arrays");
             for (int64_t t = 0; t < cnt; ++t)
@@ -470,7 +492,7 @@ bmf_status bmf_loss(bmf_ctx *c, const float hp[8], double *out) {
         if (!out || !hp) BMF_FAIL(BMF_E_INVAL, "null argument");
         if (!M.loaded) BMF_FAIL(BMF_E_STATE, "no ratings loaded");
         const HP h = hp_from(hp);
-        *out = sq_residual_sum(M, M.cu.as<int32_t>(), M.ci.as<int32_t>(), M.cr.as<float>(), M.part.nnz, &h, M.red);
+        *out = train_sq_sum(M, &h);
     });
 }
 

@@ -70,6 +70,23 @@ struct DevBuf {
     }
 };
 
+// Pinned host buffer (hipHostMalloc), for copies that overlap kernels.
+struct PinnedBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void alloc(size_t n);
+    void free_();
+    template <class T> T *as() const { return static_cast<T *>(p); }
+    ~PinnedBuf() { free_(); }
+    PinnedBuf() = default;
+    PinnedBuf(const PinnedBuf &) = delete;
+    PinnedBuf &operator=(const PinnedBuf &) = delete;
+    void swap(PinnedBuf &o) {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+    }
+};
+
 // Partition of a rating set on the device.
 struct Partition {
     int64_t nnz = 0;
@@ -103,6 +120,27 @@ struct Plan {
     }
 };
 
+// Out-of-core training data: the stratum work (planned steps or records)
+// in pinned host memory, stratum after stratum, with a block table per
+// stratum in position order; two device buffers take turns receiving a
+// stratum on the copy stream while the previous one runs.
+struct OutOfCore {
+    bool on = false;
+    int variant = 1;        // 1: records for the reference kernels, 2: planned steps
+    size_t unit = 0;        // bytes per unit (one record, or one step of PLAN_W slot records)
+    std::vector<int64_t> s_off;  // b + 1 unit offsets of the strata in `data`
+    PinnedBuf data;              // stratum-major units
+    PinnedBuf table;             // b x (b + 1) unit offsets inside each stratum, by position
+    PinnedBuf cu, ci, cr;        // the training COO as given, for RMSE and loss
+    std::vector<int32_t> perm;   // processing position -> input index
+    DevBuf stage[2], dtable[2];
+    hipStream_t copy = nullptr;
+    hipEvent_t copied[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr};
+    bool used_valid[2] = {false, false};
+    void release();
+    ~OutOfCore() { release(); }
+};
+
 // --------------------------------------------------------------- context
 struct Model {
     int device = 0;
@@ -112,6 +150,7 @@ struct Model {
     int k = 0, b = 0;
     uint64_t seed = 1001, order_seed = 2001;
     int order_mode = 0, mu_mode = 0, sgd_kernel = 0, waves = 8;
+    bool out_of_core = false;  // the next load keeps the ratings in host memory
     DevBuf P, Q, bu, bi;
     double mu = 0.0;
     // training data
@@ -119,6 +158,7 @@ struct Model {
     DevBuf cu, ci, cr;  // training COO as given (int32, int32, f32)
     Partition part;
     Plan plan;
+    OutOfCore ooc;
     int32_t epoch = 0;
     // bf16 copies for scoring
     DevBuf Pb, Qb;
@@ -175,6 +215,10 @@ int plan_kp(int k);
 int plan_slots(int kp, int64_t cb, int CH, int max_lds);
 int64_t plan_block(const uint32_t *ui, int64_t n, int ibits, int cb, int S, int CH, std::vector<PlanEntry> &out);
 void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hipStream_t s);
+// The host part of build_plan: plan the records (host, processing order)
+// into `flat`; false (out.ok false) when the planned kernel does not apply.
+bool plan_host(Plan &out, const Rec *recs, const std::vector<int64_t> &block_ptr, int ibits, int ubits, int64_t cb,
+               int b, int k, int max_lds, std::vector<SlotRec> &flat);
 // The planned kernel's fixed cost per workgroup (staging a full LDS buffer)
 // outweighs its gain on blocks of a few ratings: automatic selection takes
 // it only when the blocks hold at least PLAN_MIN_MEAN ratings on average.
@@ -185,6 +229,21 @@ void ensure_plan(Model &M);
 
 // SGD: run one epoch of strata in `order`.
 void sgd_epoch(Model &M, const int32_t *order, const HP &hp);
+// Where one stratum's work is: records (reference kernels) or steps
+// (planned kernel), and its block table, indexed br * row_stride + j.
+struct StratumData {
+    const void *data;
+    const int64_t *table;
+    int64_t row_stride;
+};
+// Launch stratum s with SGD kernel `variant` (1 or 2).
+void launch_stratum(Model &M, int s, const HP &hp, int variant, const StratumData &D);
+// Out-of-core: load host COO (validates, partitions and plans on the host),
+// run an epoch's strata with the copies overlapped, and the training
+// squared-residual sum (with the loss terms when loss_hp) in chunks.
+void ooc_load(Model &M, const int32_t *u, const int32_t *i, const float *r, int64_t nnz);
+void ooc_epoch(Model &M, const int32_t *order, const HP &hp, int variant);
+double ooc_sq_sum(Model &M, const HP *loss_hp);
 // The device's per-workgroup LDS maximum.
 int sgd_max_lds(int device);
 // One launch running the blocks items[0 .. count) of several problems

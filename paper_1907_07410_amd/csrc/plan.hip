@@ -167,23 +167,19 @@ int plan_slots(int kp, int64_t cb, int CH, int max_lds) {
     return (int)std::min<int64_t>(S, PLAN_MAX_SLOTS);
 }
 
-void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hipStream_t s) {
+bool plan_host(Plan &out, const Rec *recs, const std::vector<int64_t> &block_ptr, int ibits, int ubits, int64_t cb,
+               int b, int k, int max_lds, std::vector<SlotRec> &flat) {
     out.ok = false;
     out.built = true;
+    flat.clear();
     const int kp = plan_kp(k);
-    if (!kp || part.cb + 1 > (1 << 16) || part.ubits > 30) return;
+    if (!kp || cb + 1 > (1 << 16) || ubits > 30) return false;
     const int CH = PLAN_CH;
-    const int S = plan_slots(kp, part.cb, CH, max_lds);
-    if (S < PLAN_MIN_SLOTS) return;
-    const PlanLds L = plan_lds(kp, part.cb, S, CH);
+    const int S = plan_slots(kp, cb, CH, max_lds);
+    if (S < PLAN_MIN_SLOTS) return false;
+    const PlanLds L = plan_lds(kp, cb, S, CH);
     const int64_t nblk = (int64_t)b * b;
-    std::vector<Rec> recs(part.nnz);
-    if (part.nnz) {
-        BMF_HIP(hipMemcpyAsync(recs.data(), part.recs.p, part.nnz * sizeof(Rec), hipMemcpyDeviceToHost, s));
-        BMF_HIP(hipStreamSynchronize(s));
-    }
-    const uint32_t imask = (1u << part.ibits) - 1u;
-    const int ibits = part.ibits;
+    const uint32_t imask = (1u << ibits) - 1u;
     std::vector<std::vector<SlotRec>> per(nblk);
     std::atomic<int64_t> next{0};
     std::atomic<bool> failed{false};
@@ -195,12 +191,12 @@ void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hip
         for (;;) {
             const int64_t blk = next.fetch_add(1);
             if (blk >= nblk || failed.load()) return;
-            const int64_t beg = part.h_block_ptr[blk], end = part.h_block_ptr[blk + 1];
+            const int64_t beg = block_ptr[blk], end = block_ptr[blk + 1];
             const int64_t cnt = end - beg;
             ui.resize(cnt);
             for (int64_t x = 0; x < cnt; ++x) ui[x] = recs[beg + x].ui;
             try {
-                plan_block(ui.data(), cnt, ibits, (int)part.cb, S, CH, ent);
+                plan_block(ui.data(), cnt, ibits, (int)cb, S, CH, ent);
             } catch (const Error &e) {
                 std::lock_guard<std::mutex> g(fail_mu);
                 fail_msg = e.msg;
@@ -212,7 +208,7 @@ void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hip
             for (size_t q = 0; q < ent.size(); ++q) {
                 const int x = ent[q].x;
                 if (x < 0) {
-                    o[q] = SlotRec{(uint32_t)(L.q + (size_t)part.cb * L.row_bytes), 0.f,
+                    o[q] = SlotRec{(uint32_t)(L.q + (size_t)cb * L.row_bytes), 0.f,
                                    (uint32_t)(L.u + (size_t)S * L.row_bytes), 0u};
                     continue;
                 }
@@ -235,12 +231,28 @@ void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hip
     for (int64_t blk = 0; blk < nblk; ++blk)
         out.h_blk_step[blk + 1] = out.h_blk_step[blk] + (int64_t)per[blk].size() / PLAN_W;
     out.total_steps = out.h_blk_step[nblk];
-    std::vector<SlotRec> flat;
     flat.reserve(out.total_steps * PLAN_W);
     for (auto &v : per) {
         flat.insert(flat.end(), v.begin(), v.end());
         std::vector<SlotRec>().swap(v);
     }
+    out.kp = kp;
+    out.S = S;
+    out.CH = CH;
+    out.ok = true;
+    return true;
+}
+
+void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hipStream_t s) {
+    std::vector<Rec> recs(part.nnz);
+    if (part.nnz) {
+        BMF_HIP(hipMemcpyAsync(recs.data(), part.recs.p, part.nnz * sizeof(Rec), hipMemcpyDeviceToHost, s));
+        BMF_HIP(hipStreamSynchronize(s));
+    }
+    std::vector<SlotRec> flat;
+    if (!plan_host(out, recs.data(), part.h_block_ptr, part.ibits, part.ubits, part.cb, b, k, max_lds, flat)) return;
+    out.ok = false;
+    const int64_t nblk = (int64_t)b * b;
     out.steps.alloc(std::max<size_t>(16, flat.size() * sizeof(SlotRec)));
     out.blk_step.alloc((nblk + 1) * sizeof(int64_t));
     if (!flat.empty())
@@ -248,9 +260,6 @@ void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hip
     BMF_HIP(hipMemcpyAsync(out.blk_step.p, out.h_blk_step.data(), (nblk + 1) * sizeof(int64_t),
                            hipMemcpyHostToDevice, s));
     BMF_HIP(hipStreamSynchronize(s));
-    out.kp = kp;
-    out.S = S;
-    out.CH = CH;
     out.ok = true;
 }
 

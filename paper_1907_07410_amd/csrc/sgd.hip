@@ -67,11 +67,11 @@ __device__ __forceinline__ float residual(float r, float mu, float bu0, float bi
 template <int KPL>
 __global__ __launch_bounds__(64) void sgd_global_kernel(const Rec *__restrict__ recs,
                                                         const int64_t *__restrict__ block_ptr, int b, int s,
-                                                        int64_t rb, int64_t cb, int ibits, int k, float *P, float *Q,
-                                                        float *bu, float *bi, float mu, HP hp) {
+                                                        int64_t row_stride, int64_t rb, int64_t cb, int ibits, int k,
+                                                        float *P, float *Q, float *bu, float *bi, float mu, HP hp) {
     const int j = blockIdx.x;
     const int br = (j + s) % b;
-    const int64_t blk = (int64_t)br * b + j;
+    const int64_t blk = (int64_t)br * row_stride + j;
     const int64_t beg = block_ptr[blk], end = block_ptr[blk + 1];
     const uint32_t imask = (1u << ibits) - 1u;
     const int lane = threadIdx.x;
@@ -114,13 +114,13 @@ __global__ __launch_bounds__(64) void sgd_global_kernel(const Rec *__restrict__ 
 template <int F>
 __global__ __launch_bounds__(64) void sgd_ref16_kernel(const Rec *__restrict__ recs,
                                                        const int64_t *__restrict__ block_ptr, int b, int s,
-                                                       int64_t rb, int64_t cb, int ibits, int k, float *P, float *Q,
-                                                       float *bu, float *bi, float mu, HP hp) {
+                                                       int64_t row_stride, int64_t rb, int64_t cb, int ibits, int k,
+                                                       float *P, float *Q, float *bu, float *bi, float mu, HP hp) {
     const int row = threadIdx.x >> 4, gl = threadIdx.x & 15;
     const int j = blockIdx.x * 4 + row;
     if (j >= b) return;
     const int br = (j + s) % b;
-    const int64_t blk = (int64_t)br * b + j;
+    const int64_t blk = (int64_t)br * row_stride + j;
     const int64_t beg = block_ptr[blk], end = block_ptr[blk + 1];
     const uint32_t imask = (1u << ibits) - 1u;
     for (int64_t t = beg; t < end; ++t) {
@@ -390,17 +390,20 @@ __device__ __forceinline__ void planned_block(const SlotRec *__restrict__ steps,
     for (int x = tid; x < ncols; x += WG) bi[i0 + x] = Qs[(int64_t)x * RS + KP];
 }
 
-// One stratum s: workgroup j owns block ((j + s) mod b, j).
+// One stratum s: workgroup j owns block ((j + s) mod b, j).  Block tables
+// (here and in the reference kernels) are indexed br * row_stride + j:
+// row_stride b for tables over the whole grid, 0 for a table of the
+// stratum's own blocks in position order.
 template <int F, bool VEC, int NW>
 __global__ __launch_bounds__(NW *WAVE) void sgd_plan_kernel(const SlotRec *__restrict__ steps,
                                                             const int64_t *__restrict__ blk_step, int b, int s,
-                                                            int64_t n, int64_t rb, int64_t cb, int k, int S, int CH,
-                                                            float *P, float *Q, float *bu, float *bi, float mu,
-                                                            HP hp) {
+                                                            int64_t row_stride, int64_t n, int64_t rb, int64_t cb,
+                                                            int k, int S, int CH, float *P, float *Q, float *bu,
+                                                            float *bi, float mu, HP hp) {
     __shared__ __align__(16) unsigned char smem[PLAN_LDS_BYTES];
     const int j = blockIdx.x;
     const int br = (j + s) % b;
-    const int64_t blk = (int64_t)br * b + j;
+    const int64_t blk = (int64_t)br * row_stride + j;
     const int64_t s0 = blk_step[blk];
     planned_block<F, VEC, NW>(steps + s0 * PLAN_W, blk_step[blk + 1] - s0, (int64_t)br * rb, (int64_t)j * cb, n, cb,
                               k, S, CH, P, Q, bu, bi, mu, hp, smem);
@@ -431,28 +434,28 @@ __global__ __launch_bounds__(NW *WAVE) void sgd_positions_kernel(const BatchProb
 
 // ---------------------------------------------------------------- host
 template <int KPL>
-static void launch_global(Model &M, int s, const HP &hp) {
+static void launch_global(Model &M, int s, const HP &hp, const StratumData &D) {
     const Partition &Pt = M.part;
-    sgd_global_kernel<KPL><<<M.b, 64, 0, M.stream>>>(Pt.recs.as<Rec>(), Pt.block_ptr.as<int64_t>(), M.b, s, Pt.rb,
-                                                      Pt.cb, Pt.ibits, M.k, M.P.as<float>(), M.Q.as<float>(),
+    sgd_global_kernel<KPL><<<M.b, 64, 0, M.stream>>>(static_cast<const Rec *>(D.data), D.table, M.b, s, D.row_stride,
+                                                      Pt.rb, Pt.cb, Pt.ibits, M.k, M.P.as<float>(), M.Q.as<float>(),
                                                       M.bu.as<float>(), M.bi.as<float>(), (float)M.mu, hp);
     BMF_HIP(hipGetLastError());
 }
 
 template <int F>
-static void launch_ref16(Model &M, int s, const HP &hp) {
+static void launch_ref16(Model &M, int s, const HP &hp, const StratumData &D) {
     const Partition &Pt = M.part;
-    sgd_ref16_kernel<F><<<(M.b + 3) / 4, 64, 0, M.stream>>>(Pt.recs.as<Rec>(), Pt.block_ptr.as<int64_t>(), M.b, s,
-                                                           Pt.rb, Pt.cb, Pt.ibits, M.k, M.P.as<float>(),
-                                                           M.Q.as<float>(), M.bu.as<float>(), M.bi.as<float>(),
-                                                           (float)M.mu, hp);
+    sgd_ref16_kernel<F><<<(M.b + 3) / 4, 64, 0, M.stream>>>(static_cast<const Rec *>(D.data), D.table, M.b, s,
+                                                           D.row_stride, Pt.rb, Pt.cb, Pt.ibits, M.k,
+                                                           M.P.as<float>(), M.Q.as<float>(), M.bu.as<float>(),
+                                                           M.bi.as<float>(), (float)M.mu, hp);
     BMF_HIP(hipGetLastError());
 }
 
 template <int F, bool VEC, int NW>
-static void launch_plan(Model &M, int s, const HP &hp) {
+static void launch_plan(Model &M, int s, const HP &hp, const StratumData &D) {
     sgd_plan_kernel<F, VEC, NW><<<M.b, NW * WAVE, 0, M.stream>>>(
-        M.plan.steps.as<SlotRec>(), M.plan.blk_step.as<int64_t>(), M.b, s, M.n, M.part.rb, M.part.cb, M.k,
+        static_cast<const SlotRec *>(D.data), D.table, M.b, s, D.row_stride, M.n, M.part.rb, M.part.cb, M.k,
         M.plan.S, M.plan.CH, M.P.as<float>(), M.Q.as<float>(), M.bu.as<float>(), M.bi.as<float>(), (float)M.mu, hp);
     BMF_HIP(hipGetLastError());
 }
@@ -473,42 +476,42 @@ static int plan_key(int k, int nw) {
     return fi * 4 + (k == kp ? 2 : 0) + (nw == 8 ? 1 : 0);
 }
 
-static void launch_one(Model &M, int s, const HP &hp, int variant) {
+void launch_stratum(Model &M, int s, const HP &hp, int variant, const StratumData &D) {
     if (variant == 2) {
         switch (plan_key(M.k, M.waves)) {
-        case 0: launch_plan<1, false, 4>(M, s, hp); return;
-        case 1: launch_plan<1, false, 8>(M, s, hp); return;
-        case 2: launch_plan<1, true, 4>(M, s, hp); return;
-        case 3: launch_plan<1, true, 8>(M, s, hp); return;
-        case 4: launch_plan<2, false, 4>(M, s, hp); return;
-        case 5: launch_plan<2, false, 8>(M, s, hp); return;
-        case 6: launch_plan<2, true, 4>(M, s, hp); return;
-        case 7: launch_plan<2, true, 8>(M, s, hp); return;
-        case 8: launch_plan<4, false, 4>(M, s, hp); return;
-        case 9: launch_plan<4, false, 8>(M, s, hp); return;
-        case 10: launch_plan<4, true, 4>(M, s, hp); return;
-        case 11: launch_plan<4, true, 8>(M, s, hp); return;
-        case 12: launch_plan<8, false, 4>(M, s, hp); return;
-        case 13: launch_plan<8, false, 8>(M, s, hp); return;
-        case 14: launch_plan<8, true, 4>(M, s, hp); return;
-        default: launch_plan<8, true, 8>(M, s, hp); return;
+        case 0: launch_plan<1, false, 4>(M, s, hp, D); return;
+        case 1: launch_plan<1, false, 8>(M, s, hp, D); return;
+        case 2: launch_plan<1, true, 4>(M, s, hp, D); return;
+        case 3: launch_plan<1, true, 8>(M, s, hp, D); return;
+        case 4: launch_plan<2, false, 4>(M, s, hp, D); return;
+        case 5: launch_plan<2, false, 8>(M, s, hp, D); return;
+        case 6: launch_plan<2, true, 4>(M, s, hp, D); return;
+        case 7: launch_plan<2, true, 8>(M, s, hp, D); return;
+        case 8: launch_plan<4, false, 4>(M, s, hp, D); return;
+        case 9: launch_plan<4, false, 8>(M, s, hp, D); return;
+        case 10: launch_plan<4, true, 4>(M, s, hp, D); return;
+        case 11: launch_plan<4, true, 8>(M, s, hp, D); return;
+        case 12: launch_plan<8, false, 4>(M, s, hp, D); return;
+        case 13: launch_plan<8, false, 8>(M, s, hp, D); return;
+        case 14: launch_plan<8, true, 4>(M, s, hp, D); return;
+        default: launch_plan<8, true, 8>(M, s, hp, D); return;
         }
     }
     switch (plan_kp(M.k)) {
-    case 16: launch_ref16<1>(M, s, hp); return;
-    case 32: launch_ref16<2>(M, s, hp); return;
-    case 64: launch_ref16<4>(M, s, hp); return;
-    case 128: launch_ref16<8>(M, s, hp); return;
+    case 16: launch_ref16<1>(M, s, hp, D); return;
+    case 32: launch_ref16<2>(M, s, hp, D); return;
+    case 64: launch_ref16<4>(M, s, hp, D); return;
+    case 128: launch_ref16<8>(M, s, hp, D); return;
     default: break;
     }
     switch ((M.k + WAVE - 1) / WAVE) {
-    case 3: launch_global<3>(M, s, hp); break;
-    case 4: launch_global<4>(M, s, hp); break;
-    case 5: launch_global<5>(M, s, hp); break;
-    case 6: launch_global<6>(M, s, hp); break;
-    case 7: launch_global<7>(M, s, hp); break;
-    case 8: launch_global<8>(M, s, hp); break;
-    default: launch_global<16>(M, s, hp); break;
+    case 3: launch_global<3>(M, s, hp, D); break;
+    case 4: launch_global<4>(M, s, hp, D); break;
+    case 5: launch_global<5>(M, s, hp, D); break;
+    case 6: launch_global<6>(M, s, hp, D); break;
+    case 7: launch_global<7>(M, s, hp, D); break;
+    case 8: launch_global<8>(M, s, hp, D); break;
+    default: launch_global<16>(M, s, hp, D); break;
     }
 }
 
@@ -518,6 +521,12 @@ void ensure_plan(Model &M) {
 
 void sgd_epoch(Model &M, const int32_t *order, const HP &hp) {
     int variant = M.sgd_kernel;
+    if (M.ooc.on) {
+        if (variant == 0) variant = M.ooc.variant;
+        if (variant != M.ooc.variant)
+            BMF_FAIL(BMF_E_STATE, "out-of-core ratings were laid out for SGD kernel " + std::to_string(M.ooc.variant) +
+                                      "; set the kernel before loading");
+    }
     if (variant == 0) variant = M.plan.ok && plan_pays(M.part.nnz, M.b) ? 2 : 1;
     if (variant == 2) ensure_plan(M);
     if (variant == 2 && !M.plan.ok)
@@ -525,7 +534,13 @@ void sgd_epoch(Model &M, const int32_t *order, const HP &hp) {
                               "user slots in LDS; use SGD kernel 1 or a larger b");
     hipEvent_t ev0 = take_event(M), ev1 = take_event(M);
     BMF_HIP(hipEventRecord(ev0, M.stream));
-    for (int pos = 0; pos < M.b; ++pos) launch_one(M, order[pos], hp, variant);
+    if (M.ooc.on) {
+        ooc_epoch(M, order, hp, variant);
+    } else {
+        const StratumData D = variant == 2 ? StratumData{M.plan.steps.p, M.plan.blk_step.as<int64_t>(), M.b}
+                                           : StratumData{M.part.recs.p, M.part.block_ptr.as<int64_t>(), M.b};
+        for (int pos = 0; pos < M.b; ++pos) launch_stratum(M, order[pos], hp, variant, D);
+    }
     BMF_HIP(hipEventRecord(ev1, M.stream));
     M.pending.emplace_back(ev0, ev1);
     M.sgd_launches += M.b;

@@ -90,9 +90,9 @@ typedef enum {
     /* 1: the next load keeps the ratings in pinned host memory (out of core,
      * Section 6's unbounded block count): partition and step plans are made
      * on the host, each stratum's work is laid out contiguously, and an epoch
-     * copies stratum after stratum into one of two device buffers on a copy
-     * stream while the previous stratum runs.  Device memory then holds the
-     * factor tables and two strata.  The kernels, and so the results, are
+     * copies stratum after stratum into a ring of three device buffers on a
+     * copy stream while earlier strata run.  Device memory then holds the
+     * factor tables and three strata.  The kernels, and so the results, are
      * those of a resident load with the same SGD kernel; mu is summed on the
      * host in input order.  Such a load takes host arrays only
      * (bmf_load_ratings), fixes the SGD kernel (set BMF_OPT_SGD_KERNEL before
@@ -167,6 +167,15 @@ bmf_status bmf_epoch_hp(bmf_ctx *c, const float hp[8]);
 
 /* Number of epochs run so far (the next epoch's index). */
 bmf_status bmf_epoch_count(const bmf_ctx *c, int32_t *out);
+
+/* What the next epoch runs (Section 3's blocks, Eqs 10-13): *kernel = 2 for
+ * the LDS-staged planned kernel, 1 for the 16-lane reference kernel, 3 for
+ * the 64-lane reference kernel (k > 128), 0 when kernel 2 is forced but
+ * does not apply (the epoch would fail); *steps = the plan's total dependent
+ * steps (four ratings each) and *slots = LDS user slots per block when the
+ * planned kernel runs, else 0.  May build the plan (host, synchronises).
+ * Any output may be NULL.  Errors: BMF_E_STATE (no ratings loaded). */
+bmf_status bmf_plan_info(bmf_ctx *c, int32_t *kernel, int64_t *steps, int32_t *slots);
 
 /* Incremental data (Section 6: new ratings become new blocks that are
  * factorised on their own, then the factors converge together on all the

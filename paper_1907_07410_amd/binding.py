@@ -58,6 +58,7 @@ def _load():
         "bmf_epoch_count": ([p, p], i32),
         "bmf_fit": ([p, p, i32, dbl, p, p], i32),
         "bmf_add_ratings": ([p, i64, i64, p, p, p, i64, p, i32], i32),
+        "bmf_plan_info": ([p, p, p, p], i32),
         "bmf_get_schedule": ([p, i32, p], i32),
         "bmf_get_partition": ([p, p, p], i32),
         "bmf_get_factors": ([p, p, p, p, p, p], i32),
@@ -212,6 +213,13 @@ class Model:
         self._check(lib.bmf_add_ratings(self._h, int(m_new), int(n_new), _ptr(u), _ptr(i), _ptr(r),
                                         u.shape[0], _ptr(hp), int(epochs_new)))
         self.m, self.n = int(m_new), int(n_new)
+
+    def plan_info(self):
+        """(kernel the next epoch runs, plan steps, LDS user slots); see
+        bmf_plan_info."""
+        kern, steps, slots = C.c_int32(), C.c_int64(), C.c_int32()
+        self._check(lib.bmf_plan_info(self._h, C.byref(kern), C.byref(steps), C.byref(slots)))
+        return kern.value, steps.value, slots.value
 
     def epoch_count(self) -> int:
         out = C.c_int32()

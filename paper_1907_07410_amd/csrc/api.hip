@@ -378,6 +378,21 @@ bmf_status bmf_add_ratings(bmf_ctx *c, int64_t m_new, int64_t n_new, const int32
     });
 }
 
+bmf_status bmf_plan_info(bmf_ctx *c, int32_t *kernel, int64_t *steps, int32_t *slots) {
+    return guarded(c, false, [&] {
+        Model &M = c->M;
+        if (!M.loaded) BMF_FAIL(BMF_E_STATE, "no ratings loaded");
+        int v = M.sgd_kernel;
+        if (M.ooc.on && v == 0) v = M.ooc.variant;
+        if (v == 0) v = M.plan.ok && plan_pays(M.part.nnz, M.b) ? 2 : 1;
+        if (v == 2 && !M.ooc.on) ensure_plan(M);
+        const bool planned = v == 2 && M.plan.ok;
+        if (kernel) *kernel = v == 2 ? (planned ? 2 : 0) : (plan_kp(M.k) ? 1 : 3);
+        if (steps) *steps = planned ? M.plan.total_steps : 0;
+        if (slots) *slots = planned ? M.plan.S : 0;
+    });
+}
+
 bmf_status bmf_epoch_count(const bmf_ctx *c, int32_t *out) {
     if (!c || !out) return BMF_E_INVAL;
     *out = c->M.epoch;

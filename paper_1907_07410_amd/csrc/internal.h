@@ -121,22 +121,23 @@ struct Plan {
 };
 
 // Out-of-core training data: the stratum work (planned steps or records)
-// in pinned host memory, stratum after stratum, with a block table per
-// stratum in position order; two device buffers take turns receiving a
-// stratum on the copy stream while the previous one runs.
+// in pinned host memory, stratum after stratum, each followed by its block
+// table (b + 1 unit offsets, by position); OOC_BUFS device buffers take
+// turns receiving strata on the copy stream while earlier ones run.
+constexpr int OOC_BUFS = 3;
 struct OutOfCore {
     bool on = false;
     int variant = 1;        // 1: records for the reference kernels, 2: planned steps
     size_t unit = 0;        // bytes per unit (one record, or one step of PLAN_W slot records)
-    std::vector<int64_t> s_off;  // b + 1 unit offsets of the strata in `data`
-    PinnedBuf data;              // stratum-major units
-    PinnedBuf table;             // b x (b + 1) unit offsets inside each stratum, by position
+    std::vector<int64_t> s_off;    // b + 1 byte offsets of the strata in `data`
+    std::vector<int64_t> s_units;  // units of each stratum (its table follows them)
+    PinnedBuf data;                // stratum-major units and tables
     PinnedBuf cu, ci, cr;        // the training COO as given, for RMSE and loss
     std::vector<int32_t> perm;   // processing position -> input index
-    DevBuf stage[2], dtable[2];
+    DevBuf stage[OOC_BUFS];
     hipStream_t copy = nullptr;
-    hipEvent_t copied[2] = {nullptr, nullptr}, used[2] = {nullptr, nullptr};
-    bool used_valid[2] = {false, false};
+    hipEvent_t copied[OOC_BUFS] = {}, used[OOC_BUFS] = {};
+    bool used_valid[OOC_BUFS] = {};
     void release();
     ~OutOfCore() { release(); }
 };

@@ -2,8 +2,8 @@
 // bounded, only a block's size is (by the memory of the unit that factorises
 // it).  Here the ratings stay in pinned host memory: the partition and the
 // step plans are made on the host, the stratum work is laid out stratum after
-// stratum, and each epoch copies a stratum into one of two device buffers on
-// a copy stream while the previous stratum's kernel runs.  The factor tables
+// stratum, and each epoch copies strata into a ring of device buffers on a
+// copy stream while earlier strata's kernels run.  The factor tables
 // stay on the device.  The kernels and their results are those of the
 // resident path (the same partition, plans and launches).
 #include <algorithm>
@@ -35,23 +35,22 @@ void PinnedBuf::free_() {
 
 void OutOfCore::release() {
     if (copy) (void)hipStreamSynchronize(copy);
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < OOC_BUFS; ++q) {
         if (copied[q]) (void)hipEventDestroy(copied[q]);
         if (used[q]) (void)hipEventDestroy(used[q]);
         copied[q] = used[q] = nullptr;
         used_valid[q] = false;
         stage[q].free_();
-        dtable[q].free_();
     }
     if (copy) (void)hipStreamDestroy(copy);
     copy = nullptr;
     data.free_();
-    table.free_();
     cu.free_();
     ci.free_();
     cr.free_();
     std::vector<int32_t>().swap(perm);
     s_off.clear();
+    s_units.clear();
     on = false;
 }
 
@@ -148,30 +147,35 @@ void ooc_load(Model &M, const int32_t *u, const int32_t *i, const float *r, int6
     OutOfCore X;
     X.variant = variant;
     X.unit = unit;
+    // stratum s: its blocks' units in position order, then its table
+    const size_t tbytes = (size_t)(b + 1) * sizeof(int64_t);
     X.s_off.assign(b + 1, 0);
-    X.table.alloc((size_t)b * (b + 1) * sizeof(int64_t));
-    int64_t *tab = X.table.as<int64_t>();
-    int64_t max_units = 0;
+    X.s_units.assign(b, 0);
+    size_t max_bytes = 0;
     for (int s = 0; s < b; ++s) {
+        int64_t units = 0;
+        for (int j = 0; j < b; ++j) {
+            const int64_t blk = (int64_t)((j + s) % b) * b + j;
+            units += bptr[blk + 1] - bptr[blk];
+        }
+        X.s_units[s] = units;
+        const size_t bytes = (size_t)units * unit + tbytes;
+        X.s_off[s + 1] = X.s_off[s] + (int64_t)bytes;
+        max_bytes = std::max(max_bytes, bytes);
+    }
+    X.data.alloc((size_t)X.s_off[b]);
+    for (int s = 0; s < b; ++s) {
+        unsigned char *base = X.data.as<unsigned char>() + X.s_off[s];
+        int64_t *tab = reinterpret_cast<int64_t *>(base + (size_t)X.s_units[s] * unit);
         int64_t off = 0;
         for (int j = 0; j < b; ++j) {
             const int64_t blk = (int64_t)((j + s) % b) * b + j;
-            tab[(int64_t)s * (b + 1) + j] = off;
-            off += bptr[blk + 1] - bptr[blk];
+            const int64_t cnt = bptr[blk + 1] - bptr[blk];
+            tab[j] = off;
+            if (cnt) std::memcpy(base + (size_t)off * unit, src + (size_t)bptr[blk] * unit, (size_t)cnt * unit);
+            off += cnt;
         }
-        tab[(int64_t)s * (b + 1) + b] = off;
-        X.s_off[s + 1] = X.s_off[s] + off;
-        max_units = std::max(max_units, off);
-    }
-    X.data.alloc((size_t)X.s_off[b] * unit);
-    for (int s = 0; s < b; ++s) {
-        unsigned char *dst = X.data.as<unsigned char>() + (size_t)X.s_off[s] * unit;
-        for (int j = 0; j < b; ++j) {
-            const int64_t blk = (int64_t)((j + s) % b) * b + j;
-            const size_t bytes = (size_t)(bptr[blk + 1] - bptr[blk]) * unit;
-            if (bytes) std::memcpy(dst, src + (size_t)bptr[blk] * unit, bytes);
-            dst += bytes;
-        }
+        tab[b] = off;
     }
     X.cu.alloc((size_t)nnz * 4);
     X.ci.alloc((size_t)nnz * 4);
@@ -182,9 +186,8 @@ void ooc_load(Model &M, const int32_t *u, const int32_t *i, const float *r, int6
         std::memcpy(X.cr.p, r, nnz * 4);
     }
     X.perm.swap(perm);
-    for (int q = 0; q < 2; ++q) {
-        X.stage[q].alloc(std::max<size_t>(16, (size_t)max_units * unit));
-        X.dtable[q].alloc((size_t)(b + 1) * sizeof(int64_t));
+    for (int q = 0; q < OOC_BUFS; ++q) {
+        X.stage[q].alloc(max_bytes);
         BMF_HIP(hipEventCreateWithFlags(&X.copied[q], hipEventDisableTiming));
         BMF_HIP(hipEventCreateWithFlags(&X.used[q], hipEventDisableTiming));
     }
@@ -197,15 +200,14 @@ void ooc_load(Model &M, const int32_t *u, const int32_t *i, const float *r, int6
     std::swap(M.ooc.variant, X.variant);
     std::swap(M.ooc.unit, X.unit);
     M.ooc.s_off.swap(X.s_off);
+    M.ooc.s_units.swap(X.s_units);
     M.ooc.data.swap(X.data);
-    M.ooc.table.swap(X.table);
     M.ooc.cu.swap(X.cu);
     M.ooc.ci.swap(X.ci);
     M.ooc.cr.swap(X.cr);
     M.ooc.perm.swap(X.perm);
-    for (int q = 0; q < 2; ++q) {
+    for (int q = 0; q < OOC_BUFS; ++q) {
         M.ooc.stage[q].swap(X.stage[q]);
-        M.ooc.dtable[q].swap(X.dtable[q]);
         std::swap(M.ooc.copied[q], X.copied[q]);
         std::swap(M.ooc.used[q], X.used[q]);
     }
@@ -235,18 +237,17 @@ void ooc_epoch(Model &M, const int32_t *order, const HP &hp, int variant) {
     OutOfCore &X = M.ooc;
     const int b = M.b;
     for (int pos = 0; pos < b; ++pos) {
-        const int s = order[pos], q = pos & 1;
+        const int s = order[pos], q = pos % OOC_BUFS;
         // the buffer is free once the kernel that last read it has finished
         if (X.used_valid[q]) BMF_HIP(hipStreamWaitEvent(X.copy, X.used[q], 0));
-        const int64_t units = X.s_off[s + 1] - X.s_off[s];
-        if (units)
-            BMF_HIP(hipMemcpyAsync(X.stage[q].p, X.data.as<unsigned char>() + (size_t)X.s_off[s] * X.unit,
-                                   (size_t)units * X.unit, hipMemcpyHostToDevice, X.copy));
-        BMF_HIP(hipMemcpyAsync(X.dtable[q].p, X.table.as<int64_t>() + (int64_t)s * (b + 1),
-                               (size_t)(b + 1) * sizeof(int64_t), hipMemcpyHostToDevice, X.copy));
+        // one copy: the stratum's units and its block table behind them
+        BMF_HIP(hipMemcpyAsync(X.stage[q].p, X.data.as<unsigned char>() + X.s_off[s],
+                               (size_t)(X.s_off[s + 1] - X.s_off[s]), hipMemcpyHostToDevice, X.copy));
         BMF_HIP(hipEventRecord(X.copied[q], X.copy));
         BMF_HIP(hipStreamWaitEvent(M.stream, X.copied[q], 0));
-        launch_stratum(M, s, hp, variant, StratumData{X.stage[q].p, X.dtable[q].as<int64_t>(), 0});
+        const unsigned char *st = X.stage[q].as<unsigned char>();
+        launch_stratum(M, s, hp, variant,
+                       StratumData{st, reinterpret_cast<const int64_t *>(st + (size_t)X.s_units[s] * X.unit), 0});
         BMF_HIP(hipEventRecord(X.used[q], M.stream));
         X.used_valid[q] = true;
     }

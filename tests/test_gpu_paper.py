@@ -89,6 +89,18 @@ def test_single_block_two_epochs(orc):
     assert d <= 1e-4
 
 
+def test_plan_info_large_k():
+    from paper_1907_07410_amd import binding as B
+    prob = configs.PAPER_ML1M.generate(1, scale=0.05)
+    G = B.Model(prob.m, prob.n, 200, 4, seed=1001)
+    G.load_ratings(prob.train.u, prob.train.i, prob.train.r)
+    assert G.plan_info() == (3, 0, 0)
+    G.set_option(B.OPT_SGD_KERNEL, 2)
+    assert G.plan_info()[0] == 0
+    with pytest.raises(B.BmfError):
+        G.epoch_hp(HP)
+
+
 def test_fit_arguments(orc):
     from paper_1907_07410_amd import binding as B
     prob = configs.PAPER_ML1M.generate(1, scale=0.05)
@@ -120,6 +132,9 @@ def test_automatic_kernel_choice_identical_bits(b):
     for kern in (0, 1, 2):
         G = B.Model(prob.m, prob.n, 13, b, seed=1001, order_mode=0, sgd_kernel=kern)
         G.load_ratings(tr.u, tr.i, tr.r)
+        k_run, steps, slots = G.plan_info()
+        assert k_run == (kern if kern else (2 if b == 64 else 1))
+        assert (steps > 0 and slots >= 8) == (k_run == 2)
         for _ in range(2):
             G.epoch_hp(HP)
         out.append(G.get_factors()[:4])

@@ -32,8 +32,8 @@ MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}  # MI355X dense matrix peaks
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors
 # that make the counters match a plain 256 MiB copy kernel), valid for the
 # kernel sources with this sha1; reported as null once they change.
-SGD_TRAFFIC = {"sources_sha1": "ae027e0334a00e6b9d01777366c01d83b31604b0",
-               "fetch_bytes": 26908711.9, "write_bytes": 21915838.3}
+SGD_TRAFFIC = {"sources_sha1": "2e80137064a3985836ab971c3d203e17446b556b",
+               "fetch_bytes": 26925544.3, "write_bytes": 21915903.3}
 SGD_SOURCES = ["paper_1907_07410_amd/csrc/sgd.hip", "paper_1907_07410_amd/csrc/plan.hip",
                "paper_1907_07410_amd/csrc/plan.h", "paper_1907_07410_amd/csrc/wave.h"]
 

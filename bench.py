@@ -42,6 +42,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def measured_traffic():
     import hashlib
     h = hashlib.sha1()
@@ -107,18 +118,38 @@ def serving_leg(binding, args):
         serving.run(S, warm, K=sc.K, precision=prec)
         st = serving.run(S, reqs, K=sc.K, precision=prec)
         sat = st["req_per_s"]
-        prng = np.random.default_rng(args.seed + 12)
-        preqs = serving.make_stream(prng, n, 0.5 * sat, sc.m, sc.n, Q, bi, mu, topk_frac=sc.topk_frac,
-                                    batch_range=sc.batch_range, foldin_range=sc.foldin_range)
-        st2 = serving.run(S, preqs, K=sc.K, precision=prec)
+        sweep = []
+        for frac in (0.1, 0.5, 0.9, 1.2):
+            prng = np.random.default_rng(args.seed + 12)
+            preqs = serving.make_stream(prng, n, frac * sat, sc.m, sc.n, Q, bi, mu, topk_frac=sc.topk_frac,
+                                        batch_range=sc.batch_range, foldin_range=sc.foldin_range)
+            stp = serving.run(S, preqs, K=sc.K, precision=prec)
+            sweep.append({"load": frac, "offered_req_per_s": frac * sat, "achieved_req_per_s": stp["req_per_s"],
+                          "p50_ms": stp["p50_ms"], "p99_ms": stp["p99_ms"]})
+        st2 = sweep[1]
         out[name] = {"saturated_req_per_s": sat, "saturated_users_per_s": users / st["elapsed_s"],
                      "saturated_p50_ms": st["p50_ms"], "saturated_p99_ms": st["p99_ms"],
                      "batches": st["batches"], "poisson_offered_req_per_s": 0.5 * sat,
-                     "poisson_achieved_req_per_s": st2["req_per_s"], "poisson_p50_ms": st2["p50_ms"],
-                     "poisson_p99_ms": st2["p99_ms"]}
-        log(f"serving {name}: {sat:.1f} req/s saturated (p99 {st['p99_ms']:.1f} ms); Poisson at half: "
-            f"p50 {st2['p50_ms']:.2f} ms p99 {st2['p99_ms']:.2f} ms")
+                     "poisson_achieved_req_per_s": st2["achieved_req_per_s"], "poisson_p50_ms": st2["p50_ms"],
+                     "poisson_p99_ms": st2["p99_ms"], "poisson_sweep": sweep}
+        log(f"serving {name}: {sat:.1f} req/s saturated (p99 {st['p99_ms']:.1f} ms); Poisson p99 at 10/50/90/120%: "
+            + " / ".join(f"{x['p99_ms']:.2f}" for x in sweep) + " ms")
         S.close()
+    # fold-in latency alone (host call: upload, 10 passes, download), k = 128
+    fold = {}
+    frng = np.random.default_rng(args.seed + 13)
+    for nr in (5, 50, 500):
+        items = frng.choice(sc.n, nr, replace=False).astype(np.int32)
+        r = frng.integers(1, 6, nr).astype(np.float32)
+        G.foldin(items, r, sc.foldin_passes, sc.lr, sc.reg)
+        lat = []
+        for _ in range(20):
+            t0 = time.perf_counter()
+            G.foldin(items, r, sc.foldin_passes, sc.lr, sc.reg)
+            lat.append((time.perf_counter() - t0) * 1e3)
+        fold[str(nr)] = {"median_ms": float(np.median(lat)), "max_ms": float(np.max(lat))}
+    out["foldin_latency_k128_10_passes"] = fold
+    log("fold-in latency (5 / 50 / 500 ratings): " + " / ".join(f"{v['median_ms']:.3f}" for v in fold.values()) + " ms")
     del G
     return out
 
@@ -345,6 +376,88 @@ def out_of_core_leg(binding, args, prob, cfg):
     return out
 
 
+def large_leg(binding, args, torch):
+    """The large-scale workload (480,000 x 17,800, 90M training ratings,
+    k = 128, 128 x 128 blocks): epoch time and SGD roofline, the oracle's
+    first epoch beside it (parity and host time), then top-100 for every
+    user in FP32 and in BF16 with FP32 rescoring (GPU time with events;
+    recall on 20,000 sampled users)."""
+    from paper_1907_07410_amd import configs
+    cfg = configs.LARGE
+    t0 = time.time()
+    prob = cfg.generate(args.seed)
+    tr = prob.train
+    log(f"large: generated {len(tr)} ratings in {time.time() - t0:.1f}s")
+    abytes, _, _ = algorithmic_bytes(tr.u, tr.i, prob.m, prob.n, cfg.b, cfg.k)
+    G = binding.Model(prob.m, prob.n, cfg.k, cfg.b, seed=args.seed + 1000, order_mode=0)
+    t0 = time.perf_counter()
+    G.load_ratings(tr.u, tr.i, tr.r)
+    load_s = time.perf_counter() - t0
+    G.epoch(cfg.lr, cfg.reg)
+    G.synchronize()
+    out = {"workload": f"{prob.m} x {prob.n}, {len(tr)} training ratings, k={cfg.k}, {cfg.b}x{cfg.b} blocks",
+           "load_s": load_s}
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = max(1, min(len(os.sched_getaffinity(0)), 64))
+        O = oracle.Model(prob.m, prob.n, cfg.k, cfg.b, seed=args.seed + 1000, order_mode=0)
+        O.load(tr.u, tr.i, tr.r)
+        t0 = time.perf_counter()
+        O.epoch(cfg.lr, cfg.reg, threads=threads)
+        o_s = time.perf_counter() - t0
+        P, Q, bu, bi, _ = G.get_factors()
+        out["parity_1epoch_max_abs"] = float(max(np.abs(P - O.P).max(), np.abs(Q - O.Q).max(),
+                                                 np.abs(bu - O.bu).max(), np.abs(bi - O.bi).max()))
+        out["oracle_epoch_s"] = o_s
+        out["oracle_updates_per_s"] = len(tr) / o_s
+        out["oracle_threads"] = threads
+        del O, P, Q
+    G.sgd_timing(reset=True)
+    epochs = 3
+    G.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(epochs):
+        G.epoch(cfg.lr, cfg.reg)
+    G.synchronize()
+    el = time.perf_counter() - t0
+    ms, launches = G.sgd_timing(reset=True)
+    per_launch = ms / launches
+    out.update({"updates_per_s": len(tr) * epochs / el, "ms_per_epoch": el / epochs * 1e3,
+                "avg_launch_ms": per_launch, "algorithmic_bytes_per_epoch": abytes,
+                "achieved_GBps": abytes / cfg.b / (per_launch / 1e3) / 1e9})
+    out["frac_of_hbm_peak"] = out["achieved_GBps"] / HBM_PEAK_GBS
+    log(f"large: {out['updates_per_s'] / 1e6:.0f}M updates/s, {out['ms_per_epoch']:.1f} ms/epoch, "
+        f"{per_launch:.3f} ms per stratum, {out['achieved_GBps']:.0f} GB/s algorithmic")
+    # top-100 for every user
+    users = torch.arange(prob.m, dtype=torch.int32, device="cuda")
+    ts = torch.cuda.Stream()
+    G.set_option(binding.OPT_STREAM, ts.cuda_stream)
+    flops = 2.0 * prob.m * prob.n * cfg.k
+    res = {}
+    for name, prec, peak in (("fp32", 0, MFMA_PEAK_TFLOPS["fp32"]), ("bf16", 1, MFMA_PEAK_TFLOPS["bf16"])):
+        it = torch.empty((prob.m, 100), dtype=torch.int32, device="cuda")
+        sc = torch.empty((prob.m, 100), dtype=torch.float32, device="cuda")
+        G.topk_dev(users, 100, prec, 0, it, sc)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(ts)
+        G.topk_dev(users, 100, prec, 0, it, sc)
+        ev1.record(ts)
+        ts.synchronize()
+        dt = ev0.elapsed_time(ev1) / 1e3
+        res[name] = it[:20000].cpu().numpy()
+        out[f"topk_all_users_{name}_ms"] = dt * 1e3
+        out[f"topk_all_users_{name}_tflops"] = flops / dt / 1e12
+        out[f"topk_all_users_{name}_frac_of_mfma_peak"] = flops / dt / 1e12 / peak
+        del it, sc
+    G.set_option(binding.OPT_STREAM, 0)
+    out["recall_at_100_bf16_vs_fp32_20k_users"] = float(
+        np.mean([len(set(a) & set(b)) / 100 for a, b in zip(res["fp32"], res["bf16"])]))
+    log(f"large: top-100 for all {prob.m} users FP32 {out['topk_all_users_fp32_ms']:.1f} ms, BF16 "
+        f"{out['topk_all_users_bf16_ms']:.1f} ms, recall {out['recall_at_100_bf16_vs_fp32_20k_users']:.4f}")
+    del G
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -361,6 +474,8 @@ def main():
     ap.add_argument("--no-paper-protocol", action="store_true",
                     help="skip the MovieLens-1M-shaped early-termination leg")
     ap.add_argument("--no-out-of-core", action="store_true", help="skip the out-of-core leg")
+    ap.add_argument("--large", action="store_true",
+                    help="also run the large-scale leg (90M ratings, k=128; about two more minutes)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this many MiB (reference for HBM traffic counters)")
     args = ap.parse_args()
@@ -436,7 +551,7 @@ def main():
         one_s = time.time() - t0
         del O1
         cpu = {"value": len(tr) * cfg.epochs / cpu_s, "unit": "rating updates/s", "cores": threads,
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"{cfg.epochs} full epochs of the mid-scale workload ({len(tr)} updates each, FP64, "
                          f"{threads} threads over each stratum's blocks), {cpu_s:.1f}s",
                "single_thread_value": len(tr) / one_s,
@@ -539,6 +654,26 @@ def main():
             topk[f"max_score_error_{name}_vs_fp64"] = err[name]
         topk["users"] = len(users)
         topk["items"] = prob.n
+        # small batches: latency of one request (GPU time with events)
+        small = {}
+        G.set_option(binding.OPT_STREAM, ts.cuda_stream)
+        for nb in (1, 16, 64):
+            du_s = du[:nb].contiguous()
+            it = torch.empty((nb, 100), dtype=torch.int32, device="cuda")
+            sc = torch.empty((nb, 100), dtype=torch.float32, device="cuda")
+            row = {}
+            for name, prec in (("fp32", 0), ("bf16", 1)):
+                G.topk_dev(du_s, 100, prec, 0, it, sc)
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record(ts)
+                for _ in range(10):
+                    G.topk_dev(du_s, 100, prec, 0, it, sc)
+                ev1.record(ts)
+                ts.synchronize()
+                row[name + "_ms"] = ev0.elapsed_time(ev1) / 10
+            small[str(nb)] = row
+        G.set_option(binding.OPT_STREAM, 0)
+        topk["small_batches"] = small
 
     del G
     ooc_out = None if args.no_out_of_core else out_of_core_leg(binding, args, prob, cfg)
@@ -559,6 +694,7 @@ def main():
     batched_out = batched_leg(binding, args, torch) if args.batched_scale > 0 else None
     paper_out = None if args.no_paper_protocol else paper_leg(binding, args)
     incr_out = None if args.no_paper_protocol else incremental_leg(binding, args)
+    large_out = large_leg(binding, args, torch) if args.large else None
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
         x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -604,6 +740,7 @@ def main():
         "paper_protocol": paper_out,
         "incremental": incr_out,
         "out_of_core": ooc_out,
+        "large": large_out,
     }
     print(json.dumps(line), flush=True)
 

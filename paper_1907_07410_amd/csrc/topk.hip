@@ -428,8 +428,12 @@ __global__ __launch_bounds__(64) void filter_kernel(const float *__restrict__ Ug
     }
 }
 
-// User tiles per filter wave (two measured faster than one or four at k = 64).
-static int filter_tiles_per_wave(int kc) { return kc <= 8 ? 2 : 1; }
+// User tiles per filter wave, as measured: two at k <= 64, four at
+// 64 < k <= 128 (FP32 8 chunks, BF16 4), fewer where the user fragments
+// would not fit the registers.
+static constexpr int filter_tiles_per_wave(int kc, bool bf16) {
+    return bf16 ? (kc == 4 ? 4 : kc <= 8 ? 2 : 1) : (kc == 8 ? 4 : kc <= 4 ? 2 : 1);
+}
 // The latent chunk count the pass kernels are instantiated for.
 static int dispatch_kc(int kc) { return kc <= 2 ? kc : kc <= 4 ? 4 : kc <= 8 ? 8 : 16; }
 
@@ -627,7 +631,7 @@ static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ug
     const unsigned tiles = (unsigned)(T.nu_pad / TU);
     sample_threshold_kernel<KC, BF16><<<tiles, SMP_WAVES * WAVE, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb, T.s, T.r, thr, cnt);
     BMF_HIP(hipGetLastError());
-    constexpr int UT = KC <= 8 ? 2 : 1;
+    constexpr int UT = filter_tiles_per_wave(KC, BF16);
     if (T.ut != UT) BMF_FAIL(BMF_E_STATE, "top-K plan made for another filter shape");
     const unsigned groups = (unsigned)((tiles + UT - 1) / UT);
     filter_kernel<KC, BF16, UT><<<dim3(groups, (unsigned)T.S), 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb,
@@ -726,7 +730,7 @@ TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
         T.capg = std::max(T.capg, std::min(CAPG_MAX, round_up(need + 64, 64)));
     }
     // item splits for the filter: enough workgroups to fill the chip
-    T.ut = filter_tiles_per_wave(dispatch_kc(T.bf ? T.kb / 32 : T.kp / 16));
+    T.ut = filter_tiles_per_wave(dispatch_kc(T.bf ? T.kb / 32 : T.kp / 16), T.bf);
     const int64_t groups = (T.nu_pad / TU + T.ut - 1) / T.ut;
     int S = (int)std::max<int64_t>(1, (4096 + groups - 1) / std::max<int64_t>(groups, 1));
     S = (int)std::min<int64_t>(S, std::max<int64_t>(1, n / 256));

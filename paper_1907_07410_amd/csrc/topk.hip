@@ -437,39 +437,106 @@ static constexpr int filter_tiles_per_wave(int kc, bool bf16) {
 // The latent chunk count the pass kernels are instantiated for.
 static int dispatch_kc(int kc) { return kc <= 2 ? kc : kc <= 4 ? 4 : kc <= 8 ? 8 : 16; }
 
-// Pass 3: one workgroup per user sorts its candidates (descending keys) and
-// writes the best `need` (0 = none).  A user with fewer than `need`
-// candidates under a real threshold, or with an overflowed buffer, is
-// marked in fail[] for the full-selection kernel.
+// Pass 3: one workgroup per user keeps the candidates that can be among its
+// best `need` (a 256-bin histogram of their scores between the smallest and
+// the largest gives a cut bin; every key in the cut bin and above is kept),
+// sorts those (descending keys) and writes the best `need` (0 = none).  A
+// user with fewer than `need` candidates under a real threshold, or with an
+// overflowed buffer, is marked in fail[] for the full-selection kernel.
 constexpr int FIN_WG = 256;
 constexpr int CAPG_MAX = 4096;
+
+constexpr int FIN_BINS = 256;
 
 template <int CAP>
 __global__ __launch_bounds__(FIN_WG) void finish_kernel(const uint32_t *__restrict__ thr,
                                                         const uint32_t *__restrict__ cnt,
                                                         const uint64_t *__restrict__ cand, int capg, int need,
                                                         uint32_t *__restrict__ fail, uint64_t *__restrict__ sel) {
+    static_assert(CAP % FIN_WG == 0 && FIN_BINS == FIN_WG, "one bin per thread");
+    constexpr int PER = CAP / FIN_WG;
     __shared__ uint64_t buf[CAP];
+    __shared__ uint32_t hist[FIN_BINS];
+    __shared__ uint32_t range[2];
+    __shared__ uint32_t wsum[FIN_WG / WAVE];
+    __shared__ int kept;
+    const int tid = threadIdx.x;
     const int64_t row = blockIdx.x;
     const uint32_t c = cnt[row];
     const bool ok = c <= (uint32_t)capg && (c >= (uint32_t)need || thr[row] == 0u);
-    if (threadIdx.x == 0) fail[row] = ok ? 0u : 1u;
+    if (tid == 0) fail[row] = ok ? 0u : 1u;
     if (!ok) return;
     const int total = (int)c;
-    for (int x = threadIdx.x; x < total; x += FIN_WG) buf[x] = cand[row * capg + x];
+    // the candidates, PER per thread, in registers
+    uint64_t mine[PER];
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int x = tid + j * FIN_WG;
+        mine[j] = x < total ? cand[row * capg + x] : 0ull;
+        if (x < total) {
+            lo = min(lo, (uint32_t)(mine[j] >> 32));
+            hi = max(hi, (uint32_t)(mine[j] >> 32));
+        }
+    }
+    hist[tid] = 0u;
+    if (tid == 0) {
+        range[0] = 0xFFFFFFFFu;
+        range[1] = 0u;
+        kept = 0;
+    }
     __syncthreads();
+    int m = total;
+    if (total > need) {
+        // histogram of the score halves over [lo, hi] in 256 equal bins; the
+        // cut bin is the highest one with at least `need` keys in it and above,
+        // so every key of the best `need` is in a kept bin
+        atomicMin(&range[0], lo);
+        atomicMax(&range[1], hi);
+        __syncthreads();
+        const uint32_t L = range[0];
+        const uint64_t span = (uint64_t)(range[1] - L) + 1u;
+        auto bin_of = [&](uint64_t key) { return (int)(((uint64_t)((uint32_t)(key >> 32) - L) * FIN_BINS) / span); };
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (tid + j * FIN_WG < total) atomicAdd(&hist[bin_of(mine[j])], 1u);
+        __syncthreads();
+        // suffix sums: thread t scans bin FIN_BINS - 1 - t
+        const int lane = tid % WAVE, wave = tid / WAVE;
+        uint32_t v = hist[FIN_BINS - 1 - tid];
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const uint32_t o = __shfl_up(v, d, WAVE);
+            if (lane >= d) v += o;
+        }
+        if (lane == WAVE - 1) wsum[wave] = v;
+        __syncthreads();
+        for (int w = 0; w < wave; ++w) v += wsum[w];
+        // bins 0 .. cut have suffix >= need
+        const int cut = __syncthreads_count(v >= (uint32_t)need) - 1;
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (tid + j * FIN_WG < total && bin_of(mine[j]) >= cut) buf[atomicAdd(&kept, 1)] = mine[j];
+        __syncthreads();
+        m = kept;
+    } else {
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (tid + j * FIN_WG < total) buf[tid + j * FIN_WG] = mine[j];
+        __syncthreads();
+    }
     int lgN = 0;
-    while ((1 << lgN) < total) ++lgN;
+    while ((1 << lgN) < m) ++lgN;
     const int half_n = (1 << lgN) >> 1;
-    // bitonic sort, descending; pairs reaching past `total` are skipped
-    // (the missing keys act as the smallest)
+    // bitonic sort of buf[0 .. m), descending; pairs reaching past m are
+    // skipped (the missing keys act as the smallest)
     for (int lp = 1; lp <= lgN; ++lp) {
         const int lh = lp - 1;  // log2 of half the merged run
-        for (int idx = threadIdx.x; idx < half_n; idx += FIN_WG) {
-            const int lo = idx & ((1 << lh) - 1);
-            const int x = ((idx >> lh) << lp) + lo;
-            const int y = ((idx >> lh) << lp) + (1 << lp) - 1 - lo;
-            if (y < total) {
+        for (int idx = tid; idx < half_n; idx += FIN_WG) {
+            const int lo2 = idx & ((1 << lh) - 1);
+            const int x = ((idx >> lh) << lp) + lo2;
+            const int y = ((idx >> lh) << lp) + (1 << lp) - 1 - lo2;
+            if (y < m) {
                 const uint64_t a = buf[x], b2 = buf[y];
                 if (a < b2) {
                     buf[x] = b2;
@@ -479,10 +546,10 @@ __global__ __launch_bounds__(FIN_WG) void finish_kernel(const uint32_t *__restri
         }
         __syncthreads();
         for (int lq = lh - 1; lq >= 0; --lq) {
-            for (int idx = threadIdx.x; idx < half_n; idx += FIN_WG) {
+            for (int idx = tid; idx < half_n; idx += FIN_WG) {
                 const int x = ((idx >> lq) << (lq + 1)) + (idx & ((1 << lq) - 1));
                 const int y = x + (1 << lq);
-                if (y < total) {
+                if (y < m) {
                     const uint64_t a = buf[x], b2 = buf[y];
                     if (a < b2) {
                         buf[x] = b2;
@@ -493,7 +560,7 @@ __global__ __launch_bounds__(FIN_WG) void finish_kernel(const uint32_t *__restri
             __syncthreads();
         }
     }
-    for (int j = threadIdx.x; j < need; j += FIN_WG) sel[row * need + j] = j < total ? buf[j] : 0ull;
+    for (int j = tid; j < need; j += FIN_WG) sel[row * need + j] = j < m ? buf[j] : 0ull;
 }
 
 // Full selection for the users marked in fail[] (all items): each score is

@@ -95,14 +95,16 @@ struct SelShared {
 // worst key, and are never touched).  One wave; LDS accesses of a wave are
 // performed in order, so no barrier is needed between steps.
 __device__ __forceinline__ void wave_sort_desc(uint64_t *buf, int size) {
-    int N = 1;
-    while (N < size) N <<= 1;
+    int lgN = 0;
+    while ((1 << lgN) < size) ++lgN;
+    const int half_n = (1 << lgN) >> 1;
     const int lane = __lane_id();
-    for (int p = 2; p <= N; p <<= 1) {
-        const int half = p >> 1;
-        for (int idx = lane; idx < N / 2; idx += WAVE) {
-            const int x = (idx / half) * p + (idx % half);
-            const int y = (idx / half) * p + p - 1 - (idx % half);
+    for (int lp = 1; lp <= lgN; ++lp) {
+        const int lh = lp - 1;  // log2 of half the merged run
+        for (int idx = lane; idx < half_n; idx += WAVE) {
+            const int lo = idx & ((1 << lh) - 1);
+            const int x = ((idx >> lh) << lp) + lo;
+            const int y = ((idx >> lh) << lp) + (1 << lp) - 1 - lo;
             if (y < size) {
                 const uint64_t a = buf[x], c = buf[y];
                 if (a < c) {
@@ -111,10 +113,10 @@ __device__ __forceinline__ void wave_sort_desc(uint64_t *buf, int size) {
                 }
             }
         }
-        for (int q = half >> 1; q >= 1; q >>= 1) {
-            for (int idx = lane; idx < N / 2; idx += WAVE) {
-                const int x = (idx / q) * 2 * q + (idx % q);
-                const int y = x + q;
+        for (int lq = lh - 1; lq >= 0; --lq) {
+            for (int idx = lane; idx < half_n; idx += WAVE) {
+                const int x = ((idx >> lq) << (lq + 1)) + (idx & ((1 << lq) - 1));
+                const int y = x + (1 << lq);
                 if (y < size) {
                     const uint64_t a = buf[x], c = buf[y];
                     if (a < c) {
@@ -627,9 +629,10 @@ __global__ __launch_bounds__(64) void score_select_kernel(const float *__restric
 }
 
 // FP32 rescore of Kc candidates per user, then the best K.  One wave per
-// user; lane j takes candidates j, j + 64, ... and sums its dot product over
-// the factors in index order (one fma chain; the same every call), reading
-// the user's row from LDS.
+// user; lane j takes candidates j, j + 64, ... and sums its dot product in a
+// fixed order (four fma chains over the factors f = 0, 1, 2, 3 mod 4, then
+// (c0 + c1) + (c2 + c3); the same every call), reading the user's row from
+// LDS.
 __global__ __launch_bounds__(64) void rescore_kernel(const uint64_t *__restrict__ cand, int Kc, int K,
                                                      const float *__restrict__ Ug, int kp,
                                                      const float *__restrict__ Qf, const float *__restrict__ bi,
@@ -647,17 +650,24 @@ __global__ __launch_bounds__(64) void rescore_kernel(const uint64_t *__restrict_
             const int32_t item = key_item(key);
             const float *q = Qf + (int64_t)item * k;
             float d = 0.f;
+            float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
             if (vec) {
                 for (int f = 0; f < k; f += 4) {
                     const float4 qv = *reinterpret_cast<const float4 *>(q + f);
-                    d = f == 0 ? pu[0] * qv.x : fmaf(pu[f], qv.x, d);
-                    d = fmaf(pu[f + 1], qv.y, d);
-                    d = fmaf(pu[f + 2], qv.z, d);
-                    d = fmaf(pu[f + 3], qv.w, d);
+                    c0 = fmaf(pu[f], qv.x, c0);
+                    c1 = fmaf(pu[f + 1], qv.y, c1);
+                    c2 = fmaf(pu[f + 2], qv.z, c2);
+                    c3 = fmaf(pu[f + 3], qv.w, c3);
                 }
             } else {
-                for (int f = 0; f < k; ++f) d = f == 0 ? pu[0] * q[0] : fmaf(pu[f], q[f], d);
+                for (int f = 0; f < k; f += 4) {
+                    c0 = fmaf(pu[f], q[f], c0);
+                    if (f + 1 < k) c1 = fmaf(pu[f + 1], q[f + 1], c1);
+                    if (f + 2 < k) c2 = fmaf(pu[f + 2], q[f + 2], c2);
+                    if (f + 3 < k) c3 = fmaf(pu[f + 3], q[f + 3], c3);
+                }
             }
+            d = (c0 + c1) + (c2 + c3);
             nk = rank_key(d + bi[item], item);
         }
         buf[j] = nk;

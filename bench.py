@@ -580,6 +580,18 @@ def main():
     per_launch_ms = sgd_ms / max(1, launches)
     achieved = (abytes / cfg.b) / (per_launch_ms / 1e3) / 1e9
     log(f"{args.steps} steps in {el:.3f}s; sgd kernels {sgd_ms:.2f} ms over {launches} launches; test rmse {rmse:.4f}")
+    # the dependency-chain view of the same launches: every block runs its
+    # plan's steps (four independent ratings each) one after another, and a
+    # stratum lasts as long as its longest block
+    kern, plan_steps, slots, blk_steps = G.plan_info(per_block=True)
+    crit_steps = int(sum(max(blk_steps[(j + s) % cfg.b, j] for j in range(cfg.b)) for s in range(cfg.b)))
+    epoch_kernel_ms = sgd_ms / max(1, launches) * cfg.b
+    chain = {"kernel": kern, "plan_steps_per_epoch": plan_steps, "ratings_per_step": len(tr) / max(1, plan_steps),
+             "lds_user_slots": slots, "critical_steps_per_epoch": crit_steps,
+             "ns_per_critical_step": epoch_kernel_ms * 1e6 / max(1, crit_steps),
+             "cycles_per_critical_step_at_2p4GHz": epoch_kernel_ms * 1e-3 * 2.4e9 / max(1, crit_steps)}
+    log(f"chain: {crit_steps} critical steps per epoch, {chain['ns_per_critical_step']:.0f} ns "
+        f"({chain['cycles_per_critical_step_at_2p4GHz']:.0f} cycles) each")
 
     # test-RMSE pass alone, timed with events on torch's stream (the
     # library's stream is pointed at it): algorithmic bytes = the COO once
@@ -732,6 +744,7 @@ def main():
         "parity_1epoch_max_abs": parity,
         "rmse_match": match,
         "critical_path_ratings_per_epoch": cp,
+        "sgd_chain": chain,
         "load_s": load_s,
         "rmse_pass": rmse_out,
         "topk": topk,

@@ -172,10 +172,11 @@ bmf_status bmf_epoch_count(const bmf_ctx *c, int32_t *out);
  * the LDS-staged planned kernel, 1 for the 16-lane reference kernel, 3 for
  * the 64-lane reference kernel (k > 128), 0 when kernel 2 is forced but
  * does not apply (the epoch would fail); *steps = the plan's total dependent
- * steps (four ratings each) and *slots = LDS user slots per block when the
- * planned kernel runs, else 0.  May build the plan (host, synchronises).
+ * steps (four ratings each), *slots = LDS user slots per block and
+ * block_steps[b*b] = each block's steps (block id row * b + column) when the
+ * planned kernel runs, else zeros.  May build the plan (host, synchronises).
  * Any output may be NULL.  Errors: BMF_E_STATE (no ratings loaded). */
-bmf_status bmf_plan_info(bmf_ctx *c, int32_t *kernel, int64_t *steps, int32_t *slots);
+bmf_status bmf_plan_info(bmf_ctx *c, int32_t *kernel, int64_t *steps, int32_t *slots, int64_t *block_steps);
 
 /* Incremental data (Section 6: new ratings become new blocks that are
  * factorised on their own, then the factors converge together on all the

@@ -58,7 +58,7 @@ def _load():
         "bmf_epoch_count": ([p, p], i32),
         "bmf_fit": ([p, p, i32, dbl, p, p], i32),
         "bmf_add_ratings": ([p, i64, i64, p, p, p, i64, p, i32], i32),
-        "bmf_plan_info": ([p, p, p, p], i32),
+        "bmf_plan_info": ([p, p, p, p, p], i32),
         "bmf_get_schedule": ([p, i32, p], i32),
         "bmf_get_partition": ([p, p, p], i32),
         "bmf_get_factors": ([p, p, p, p, p, p], i32),
@@ -214,12 +214,15 @@ class Model:
                                         u.shape[0], _ptr(hp), int(epochs_new)))
         self.m, self.n = int(m_new), int(n_new)
 
-    def plan_info(self):
-        """(kernel the next epoch runs, plan steps, LDS user slots); see
-        bmf_plan_info."""
+    def plan_info(self, per_block: bool = False):
+        """(kernel the next epoch runs, plan steps, LDS user slots), plus the
+        steps of every block (b x b array) when per_block; see bmf_plan_info."""
         kern, steps, slots = C.c_int32(), C.c_int64(), C.c_int32()
-        self._check(lib.bmf_plan_info(self._h, C.byref(kern), C.byref(steps), C.byref(slots)))
-        return kern.value, steps.value, slots.value
+        blocks = np.zeros((self.b, self.b), dtype=np.int64) if per_block else None
+        self._check(lib.bmf_plan_info(self._h, C.byref(kern), C.byref(steps), C.byref(slots),
+                                      _ptr(blocks) if per_block else None))
+        out = (kern.value, steps.value, slots.value)
+        return out + (blocks,) if per_block else out
 
     def epoch_count(self) -> int:
         out = C.c_int32()

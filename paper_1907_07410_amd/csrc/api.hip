@@ -378,7 +378,7 @@ bmf_status bmf_add_ratings(bmf_ctx *c, int64_t m_new, int64_t n_new, const int32
     });
 }
 
-bmf_status bmf_plan_info(bmf_ctx *c, int32_t *kernel, int64_t *steps, int32_t *slots) {
+bmf_status bmf_plan_info(bmf_ctx *c, int32_t *kernel, int64_t *steps, int32_t *slots, int64_t *block_steps) {
     return guarded(c, false, [&] {
         Model &M = c->M;
         if (!M.loaded) BMF_FAIL(BMF_E_STATE, "no ratings loaded");
@@ -390,6 +390,11 @@ bmf_status bmf_plan_info(bmf_ctx *c, int32_t *kernel, int64_t *steps, int32_t *s
         if (kernel) *kernel = v == 2 ? (planned ? 2 : 0) : (plan_kp(M.k) ? 1 : 3);
         if (steps) *steps = planned ? M.plan.total_steps : 0;
         if (slots) *slots = planned ? M.plan.S : 0;
+        if (block_steps) {
+            const int64_t nb = (int64_t)M.b * M.b;
+            for (int64_t x = 0; x < nb; ++x)
+                block_steps[x] = planned ? M.plan.h_blk_step[x + 1] - M.plan.h_blk_step[x] : 0;
+        }
     });
 }
 

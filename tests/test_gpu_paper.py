@@ -135,6 +135,12 @@ def test_automatic_kernel_choice_identical_bits(b):
         k_run, steps, slots = G.plan_info()
         assert k_run == (kern if kern else (2 if b == 64 else 1))
         assert (steps > 0 and slots >= 8) == (k_run == 2)
+        blocks = G.plan_info(per_block=True)[3]
+        assert blocks.shape == (b, b) and blocks.sum() == steps
+        if k_run == 2:  # four ratings per step at most
+            bp = G.get_partition(len(tr))[0]
+            cnt = np.diff(bp).reshape(b, b)
+            assert np.all(blocks * 4 >= cnt)
         for _ in range(2):
             G.epoch_hp(HP)
         out.append(G.get_factors()[:4])

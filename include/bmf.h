@@ -200,7 +200,8 @@ bmf_status bmf_add_ratings(bmf_ctx *c, int64_t m_new, int64_t n_new, const int32
 
 /* Algorithm 1's loop: epochs with the pairs hp (as bmf_epoch_hp) until the
  * training RMSE improves by less than delta over the previous epoch (the
- * first epoch compares with the RMSE before it), at most max_epochs.
+ * first epoch compares with the RMSE before it), at most max_epochs; an
+ * epoch whose RMSE is not a number (diverged training) also ends the loop.
  * *epochs_out receives the epochs run, *rmse_out the final training RMSE
  * (either may be NULL).  Synchronises after every epoch (the RMSE).
  * Errors: BMF_E_INVAL (hp NULL or not finite, max_epochs < 0, delta not

@@ -176,7 +176,7 @@ class Model:
             self.epoch(hp=hp, threads=threads)
             done += 1
             cur = self.rmse()
-            if prev - cur < delta:
+            if not (prev - cur >= delta):  # also stops once the RMSE is not a number
                 return done, cur
             prev = cur
         return done, prev

@@ -320,11 +320,9 @@ bmf_status bmf_fit(bmf_ctx *c, const float hp[8], int32_t max_epochs, double del
             run_epoch(c, h);
             ++done;
             const double cur = train_rmse();
-            if (prev - cur < delta) {
-                prev = cur;
-                break;
-            }
+            const bool improved = prev - cur >= delta;  // false also once the RMSE is not a number
             prev = cur;
+            if (!improved) break;
         }
         if (epochs_out) *epochs_out = done;
         if (rmse_out) *rmse_out = prev;

@@ -117,6 +117,10 @@ def test_fit_arguments(orc):
     E = B.Model(10, 10, 4, 2)
     with pytest.raises(B.BmfError):
         E.fit(HP, 3, DELTA)
+    # diverging rates: the loop ends at the first RMSE that is not finite
+    D, _ = models(orc, prob, 4)
+    e, r = D.fit((5.0, 0.0) * 4, 60, DELTA)
+    assert e < 60 and not np.isfinite(r)
 
 
 @pytest.mark.parametrize("b", [64, 512])

@@ -79,3 +79,11 @@ def test_paper_pairs_reduce_training_rmse(orc):
     r0 = O.rmse()
     e, r = O.fit(configs.PAPER_HP, 30, 1e-4)
     assert r < r0
+
+
+def test_diverging_fit_stops(orc, small):
+    """Rates far too large blow the factors up; the loop ends at the first
+    epoch whose RMSE is not a number instead of running every step."""
+    O = make(orc, small)
+    e, r = O.fit((5.0, 0.0) * 4, 60, 1e-4)
+    assert e < 60 and not np.isfinite(r)

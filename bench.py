@@ -480,8 +480,7 @@ def main():
                     help="also run a plain device copy of this many MiB (reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (sharding is described in "
-              "DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only (there is no multi-GPU path); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.warmup < 1:
         args.warmup = 1

@@ -111,7 +111,7 @@ def serving_leg(binding, args):
            "mix": f"{int(sc.topk_frac * 100)}% top-{sc.K} for log-uniform {sc.batch_range} users, "
                   f"rest fold-in of log-uniform {sc.foldin_range} ratings"}
     users = sum(len(r.users) for r in reqs if r.kind == "topk")
-    for name, kw, prec in (("bf16_continuous_batching", dict(max_batches=2), 1),
+    for name, kw, prec in (("bf16_continuous_batching", dict(), 1),
                            ("fp32_one_request_per_batch", dict(max_batches=1, max_requests_per_batch=1), 0)):
         S = binding.Server(G, mem_budget_bytes=4 << 30, foldin_passes=sc.foldin_passes, foldin_lr=sc.lr,
                            foldin_reg=sc.reg, **kw)

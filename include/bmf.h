@@ -356,9 +356,10 @@ bmf_status bmf_batch_timing(bmf_batch *B, double *ms, int64_t *launches, int32_t
  * as much pinned host memory) is allocated at creation; no allocation
  * happens per request. */
 typedef struct {
-    int64_t mem_budget_bytes;       /* device workspace for in-flight batches (0: 256 MiB) */
-    int32_t max_batches;            /* batches on the GPU at once, 1..4 (0: 2) */
-    int32_t max_batch_rows;         /* users per batch, top-K users plus fold-ins (0: 16384) */
+    int64_t mem_budget_bytes;       /* device workspace for in-flight batches (0: 1 GiB) */
+    int32_t max_batches;            /* batches on the GPU at once, 1..4 (0: 4) */
+    int32_t max_batch_rows;         /* users per batch, top-K users plus fold-ins (0: 4096); the first
+                                       request of a batch is taken whatever its size */
     int32_t max_requests_per_batch; /* 0: unlimited; 1 turns batching off */
     int32_t foldin_passes;          /* passes of a fold-in (0: 10) */
     float foldin_lr, foldin_reg;    /* fold-in step and regulariser (0: 0.005, 0.05) */

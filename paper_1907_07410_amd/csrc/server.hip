@@ -291,6 +291,14 @@ void finish_batch(bmf_server *S, Slot &sl) {
     sl.busy = false;
 }
 
+// Releases a held lock for a scope and takes it back on exit (also when an
+// exception leaves the scope).
+struct UnlockGuard {
+    std::unique_lock<std::mutex> &lk;
+    explicit UnlockGuard(std::unique_lock<std::mutex> &l) : lk(l) { lk.unlock(); }
+    ~UnlockGuard() { lk.lock(); }
+};
+
 void scheduler(bmf_server *S) {
     std::unique_lock<std::mutex> lk(S->mu);
     try {
@@ -360,7 +368,12 @@ void scheduler(bmf_server *S) {
                 S->peak_bytes = std::max(S->peak_bytes, S->bytes_in_use);
                 S->batches += 1;
                 S->rows += rows;
-                launch_batch(S, sl);
+                {
+                    // the slot and its requests are the scheduler's alone now:
+                    // submissions and polls go on while the batch is launched
+                    UnlockGuard ug(lk);
+                    launch_batch(S, sl);
+                }
                 progressed = true;
             }
             if (S->stop && S->queue.empty()) {
@@ -407,6 +420,7 @@ bmf_status guarded_server(bmf_server *S, F &&f) {
 }
 
 bmf_status submit(bmf_server *S, std::shared_ptr<Request> r, int64_t *id) {
+    const Clock::time_point t0 = Clock::now();  // latency counts from the call, including any wait for the queue
     return guarded_server(S, [&] {
         if (!id) BMF_FAIL(BMF_E_INVAL, "null id");
         Model &M = S->ctx->M;
@@ -431,7 +445,7 @@ bmf_status submit(bmf_server *S, std::shared_ptr<Request> r, int64_t *id) {
                                       std::to_string(S->part_bytes));
         }
         r->id = S->next_id++;
-        r->t_submit = Clock::now();
+        r->t_submit = t0;
         S->live[r->id] = r;
         S->queue.push_back(r);
         S->submitted += 1;

@@ -11,6 +11,13 @@ epoch, then top-100 for 20,000 users in FP32 (every answer epsilon-valid
 against FP64 scores on sampled users) and in BF16 with FP32 rescoring
 (recall@100 against FP32 of at least 0.99).
 
+Serving tables (1,000,000 x 100,000, k = 128): server results equal the
+direct BF16 calls, BF16 recall against FP32 of at least 0.99, epsilon-valid
+answers on sampled users.
+
+Batched workload at the benchmark's 1/4 scale: sampled problems equal the
+same problems trained alone, bit for bit.
+
 The oracle runs its threaded stratum mode (identical results for any thread
 count)."""
 import os
@@ -96,3 +103,68 @@ def test_large_scale_parity_and_bf16_scoring(orc):
     pick = rng.choice(len(users), 24, replace=False)
     eps_valid(fi[pick], fs[pick], P, Q, bu, bi, mu, users[pick], K, (cfg.k + 8) * 2.0 ** -23)
     eps_valid(bi_[pick], bs[pick], P, Q, bu, bi, mu, users[pick], K, (cfg.k + 8) * 2.0 ** -23)
+
+
+def test_serving_tables_full_size():
+    """The serving workload's tables (1,000,000 x 100,000, k = 128): through
+    the server with its default configuration, a mixed stream's top-100
+    results equal the direct BF16 calls bit for bit, BF16 recall against FP32
+    is at least 0.99, and sampled users' answers are epsilon-valid against
+    FP64 scores."""
+    from paper_1907_07410_amd import binding as B, serving, synth
+    from test_gpu_parity import eps_valid
+    sc = configs.SERVING
+    P, Q, bu, bi, mu = synth.serving_factors(sc.m, sc.n, sc.k, seed=5)
+    G = B.Model(sc.m, sc.n, sc.k, 1)
+    G.set_factors(P, Q, bu, bi, mu)
+    rng = np.random.default_rng(21)
+    reqs = [r for r in serving.make_stream(rng, 40, 0, sc.m, sc.n, Q, bi, mu, topk_frac=1.0,
+                                           batch_range=(1, 2048))]
+    S = B.Server(G, mem_budget_bytes=2 << 30)
+    ids = [S.submit_topk(r.users, sc.K, 1) for r in reqs]
+    S.drain()
+    users_all, items_srv = [], []
+    for r, rid in zip(reqs, ids):
+        res = S.poll(rid, wait=True)
+        di, ds = G.topk_bf16(r.users, sc.K)
+        assert np.array_equal(res["items"], di) and np.array_equal(res["scores"].view(np.uint32), ds.view(np.uint32))
+        users_all.append(r.users)
+        items_srv.append(di)
+    S.close()
+    users = np.concatenate(users_all)
+    bf = np.concatenate(items_srv)
+    fi, fs = G.topk(users, sc.K)
+    recall = float(np.mean([len(set(a) & set(b)) / sc.K for a, b in zip(fi, bf)]))
+    log("serving tables: bf16 recall@100 vs fp32 over", len(users), "users:", recall)
+    assert recall >= 0.99
+    pick = rng.choice(len(users), 16, replace=False)
+    bs = np.concatenate([G.topk_bf16(users[pick], sc.K)[1]])
+    eps_valid(bf[pick], bs, P, Q, bu, bi, mu, users[pick], sc.K, (sc.k + 8) * 2.0 ** -23)
+    eps_valid(fi[pick], fs[pick], P, Q, bu, bi, mu, users[pick], sc.K, (sc.k + 8) * 2.0 ** -23)
+
+
+def test_batched_quarter_scale_equals_alone():
+    """The batched workload at the benchmark's scale (64 problems, users and
+    items at 1/4): after two batched epochs with autotuned grids, eight of
+    the problems equal the same problems trained alone on the same grids,
+    bit for bit."""
+    from paper_1907_07410_amd import binding as B
+    bc = configs.BATCHED
+    probs = bc.generate(1, 0.25)
+    bt = B.Batch([(p.m, p.n) for p in probs], bc.k, seed=1001)
+    for q, p in enumerate(probs):
+        bt.load(q, p.train.u, p.train.i, p.train.r)
+    bt.tune()
+    bt.epochs(2, bc.lr, bc.reg)
+    for q in range(0, 64, 8):
+        p = probs[q]
+        b = bt.info(q)[0]
+        G = B.Model(p.m, p.n, bc.k, b, seed=1001)
+        G.load_ratings(p.train.u, p.train.i, p.train.r)
+        for _ in range(2):
+            G.epoch(bc.lr, bc.reg)
+        got, want = bt.problem(q).get_factors(), G.get_factors()
+        for x, y in zip(got[:4], want[:4]):
+            assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), q
+        log("batched problem", q, "grid", b, "ratings", len(p.train), "bit-identical")
+    bt.close()

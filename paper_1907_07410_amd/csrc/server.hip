@@ -248,7 +248,6 @@ void launch_batch(bmf_server *S, Slot &sl) {
         }
     }
     BMF_HIP(hipEventRecord(sl.done, sl.stream));
-    sl.busy = true;
 }
 
 void finish_batch(bmf_server *S, Slot &sl) {
@@ -368,6 +367,9 @@ void scheduler(bmf_server *S) {
                 S->peak_bytes = std::max(S->peak_bytes, S->bytes_in_use);
                 S->batches += 1;
                 S->rows += rows;
+                // busy before the lock is released, so that a drain never sees
+                // the batch's requests neither queued nor in a busy slot
+                sl.busy = true;
                 {
                     // the slot and its requests are the scheduler's alone now:
                     // submissions and polls go on while the batch is launched

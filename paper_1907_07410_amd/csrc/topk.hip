@@ -353,12 +353,18 @@ __global__ __launch_bounds__(64) void filter_kernel(const float *__restrict__ Ug
     const int nt = (int)std::min<int64_t>(UT, tiles - tile0);  // wave-uniform
     for (int x = lane; x < UT * TU; x += WAVE) lcnt[x] = 0u;
     UserFrag<KC, BF16> U[UT];
-    uint32_t t[UT];
+    // thresholds as floats: sv >= tf passes every score whose ordered key
+    // reaches the threshold (and, at most, a -0 against a +0 threshold too);
+    // no threshold (0) passes everything
+    float tf[UT];
+    bool all[UT];
 #pragma unroll
     for (int q = 0; q < UT; ++q) {
         const int64_t urow = (tile0 + (q < nt ? q : 0)) * TU + ucol;
         U[q].load(Ug, Ugb, urow, kp, kb, grp);
-        t[q] = thr[urow];
+        const uint32_t t = thr[urow];
+        all[q] = t == 0u;
+        tf[q] = t == 0u ? -INFINITY : ordered_to_float(t);
     }
     __syncthreads();
     // item biases of this lane's four score items of a tile
@@ -389,7 +395,8 @@ __global__ __launch_bounds__(64) void filter_kernel(const float *__restrict__ Ug
             pass[q] = 0u;
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
-                const bool ok = q < nt && ib + 4 * grp + rr < iend && float_to_ordered(acc[q][rr] + b[rr]) >= t[q];
+                const float sv = acc[q][rr] + b[rr];
+                const bool ok = q < nt && ib + 4 * grp + rr < iend && (all[q] || sv >= tf[q]);
                 pass[q] |= ok ? 1u << rr : 0u;
             }
         }

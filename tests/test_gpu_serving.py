@@ -134,3 +134,20 @@ def test_server_rejects_candidate_counts_beyond_selection_capacity(B, model):
             B.Server(G, Kc=kc)
         assert ex.value.status == B.BMF_E_INVAL
     B.Server(G, Kc=1008).close()
+
+
+def test_drain_waits_for_every_request(B, model):
+    """After drain, every submitted request is finished: the scheduler marks
+    a slot busy before it lets go of the queue to launch the batch, so a
+    drain cannot slip between the queue emptying and the batch starting."""
+    G, (P, Q, bu, bi, mu) = model
+    S = B.Server(G)
+    rng = np.random.default_rng(17)
+    for rep in range(6):
+        reqs = serving.make_stream(rng, 80, 0, G.m, G.n, Q, bi, mu, batch_range=(1, 300))
+        ids = [S.submit_topk(r.users, 50, rep % 2) if r.kind == "topk" else
+               S.submit_foldin(r.items, r.ratings, 50, rep % 2) for r in reqs]
+        S.drain()
+        for rid in ids:
+            assert S.poll(rid, wait=False) is not None, (rep, rid)
+    S.close()

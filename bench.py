@@ -163,15 +163,25 @@ def batched_leg(binding, args, torch):
     from paper_1907_07410_amd import configs
     bc = configs.BATCHED
     t0 = time.time()
-    probs = bc.generate(args.seed, args.batched_scale)
+    done = []
+
+    def progress(p):
+        done.append(p)
+        if len(done) % 16 == 0:
+            log(f"batched: {len(done)} of {bc.nprob} problems generated ({time.time() - t0:.0f}s)")
+
+    probs = bc.generate(args.seed, args.batched_scale, workers=min(16, os.cpu_count() or 1), progress=progress)
     nnz = [len(p.train) for p in probs]
     log(f"batched: {len(probs)} problems, {sum(nnz)} ratings generated in {time.time() - t0:.1f}s")
     bt = binding.Batch([(p.m, p.n) for p in probs], bc.k, seed=args.seed + 1000)
+    t0 = time.time()
     for q, p in enumerate(probs):
         bt.load(q, p.train.u, p.train.i, p.train.r)
+    log(f"batched: loaded in {time.time() - t0:.1f}s")
     t0 = time.time()
     bt.tune()
     tune_s = time.time() - t0
+    log(f"batched: grids and waves chosen in {tune_s:.1f}s")
     grids = [bt.info(q)[0] for q in range(len(probs))]
     waves = bt.info(0)[1]
     bt.epochs(1, bc.lr, bc.reg)
@@ -189,11 +199,30 @@ def batched_leg(binding, args, torch):
         G.epoch(bc.lr, bc.reg)
         G.synchronize()
         alone_ms += G.sgd_timing(reset=True)[0]
+    # Properties that hold at any size: every problem's training RMSE is
+    # finite, and sampled problems (the largest, the smallest, two more)
+    # equal the same problem trained alone on its grid for as many epochs
+    # (1 + epochs batched, then the one alone epoch above), bit for bit.
+    train_rmse = [bt.problem(q).rmse() for q in range(len(probs))]
+    picks = sorted({int(np.argmax(nnz)), int(np.argmin(nnz)), 0, len(probs) // 2})
+    same = {}
+    for q in picks:
+        p = probs[q]
+        G = binding.Model(p.m, p.n, bc.k, bt.info(q)[0], seed=args.seed + 1000)
+        G.load_ratings(p.train.u, p.train.i, p.train.r)
+        for _ in range(bc.epochs + 2):
+            G.epoch(bc.lr, bc.reg)
+        got, want = bt.problem(q).get_factors(), G.get_factors()
+        same[str(q)] = all(np.array_equal(x.view(np.uint32), y.view(np.uint32)) for x, y in zip(got[:4], want[:4]))
+        G.close()
+    log(f"batched: train RMSE {min(train_rmse):.4f}-{max(train_rmse):.4f}; alone bit-identical {same}")
     out = {"problems": len(probs), "scale": args.batched_scale, "ratings": int(sum(nnz)), "k": bc.k,
            "epochs": bc.epochs, "updates_per_s": sum(nnz) * bc.epochs / el, "epoch_ms": el * 1e3 / bc.epochs,
            "kernel_ms_per_epoch": ms / bc.epochs, "launches_per_epoch": launches / bc.epochs,
            "alone_sequential_epoch_ms": alone_ms, "speedup_vs_alone": alone_ms / (ms / bc.epochs),
-           "tune_s": tune_s, "waves": waves, "grids": {str(b): grids.count(b) for b in sorted(set(grids))}}
+           "tune_s": tune_s, "waves": waves, "grids": {str(b): grids.count(b) for b in sorted(set(grids))},
+           "train_rmse_range": [min(train_rmse), max(train_rmse)],
+           "alone_bit_identical": same}
     log(f"batched: {out['updates_per_s'] / 1e6:.0f}M updates/s, epoch {out['epoch_ms']:.2f} ms "
         f"(alone one after another {alone_ms:.2f} ms), grids {out['grids']}, waves {waves}, tune {tune_s:.1f}s")
     bt.close()
@@ -461,7 +490,7 @@ def large_leg(binding, args, torch):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -469,7 +498,7 @@ def main():
     ap.add_argument("--sgd-kernel", type=int, default=0)
     ap.add_argument("--serving-requests", type=int, default=1000,
                     help="requests per serving measurement (0 skips the serving leg)")
-    ap.add_argument("--batched-scale", type=float, default=0.25,
+    ap.add_argument("--batched-scale", type=float, default=1.0,
                     help="linear scale of the 64-problem batched workload's m and n (0 skips the batched leg)")
     ap.add_argument("--no-paper-protocol", action="store_true",
                     help="skip the MovieLens-1M-shaped early-termination leg")

@@ -117,14 +117,32 @@ class BatchedConfig:
             out.append((m2, n2, max(1, int(round(d * m2 * n2)))))
         return out
 
-    def generate(self, seed: int = 1, scale: float = 1.0) -> List[synth.Problem]:
-        probs = []
-        for p, (m, n, nnz) in enumerate(self.shapes(seed, scale)):
+    def generate(self, seed: int = 1, scale: float = 1.0, workers: int = 1,
+                 progress=None) -> List[synth.Problem]:
+        """The problems at ``scale``.  Problem p draws from its own generator
+        (seed * 1000 + p), so ``workers`` threads give the same data as one;
+        numpy's sorting and sampling release the interpreter lock, which is
+        what lets threads help (the full size is about 1e9 ratings).
+        ``progress(p)``, if given, is called as problem p is finished."""
+        shapes = self.shapes(seed, scale)
+
+        def one(p: int) -> synth.Problem:
+            m, n, nnz = shapes[p]
             rng = np.random.default_rng(seed * 1000 + p)
             u, i = synth.sample_pairs_zipf(m, n, nnz, 1.1, 1.1, rng)
             r = synth.planted_values(u, i, m, n, self.rank, 0.3, self.noise, 3.5, "int", rng)
-            probs.append(synth.Problem(m, n, synth.Ratings(u, i, r), None))
-        return probs
+            if progress is not None:
+                progress(p)
+            return synth.Problem(m, n, synth.Ratings(u, i, r), None)
+
+        if workers <= 1:
+            return [one(p) for p in range(len(shapes))]
+        from concurrent.futures import ThreadPoolExecutor
+        # largest problems first, so the longest draw starts at once
+        order = sorted(range(len(shapes)), key=lambda p: -shapes[p][2])
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            done = dict(zip(order, ex.map(one, order)))
+        return [done[p] for p in range(len(shapes))]
 
 
 BATCHED = BatchedConfig()

@@ -37,6 +37,17 @@ def test_mid_workload_half_stars_small_scale():
     assert r.min() >= 0.5 and r.max() <= 5.0 and np.all(np.round(r * 2) == r * 2)
 
 
+def test_batched_generation_same_with_threads():
+    bc = configs.BATCHED
+    one = bc.generate(3, scale=0.02)
+    many = bc.generate(3, scale=0.02, workers=4)
+    assert len(one) == len(many) == bc.nprob
+    for a, c in zip(one, many):
+        assert (a.m, a.n) == (c.m, c.n)
+        assert np.array_equal(a.train.u, c.train.u) and np.array_equal(a.train.i, c.train.i)
+        assert np.array_equal(a.train.r, c.train.r)
+
+
 def brute(u, i, m, n, b, k):
     rb, cb = -(-m // b), -(-n // b)
     users, items = set(), set()

@@ -87,6 +87,31 @@ def critical_path(u, i, m, n, b, order_mode=0):
     return int(tot), int(cnt.max()), float(cnt.mean())
 
 
+def tables_recall(G, P, Q, bu, bi, mu, K, users, n64=32):
+    """Top-K of ``users`` in FP32 and in BF16 with FP32 rescoring: BF16
+    recall@K against FP32, and both against FP64 scores of the same factors
+    on the first ``n64`` users (recall and the largest score error)."""
+    f_it, f_sc = G.topk(users, K)
+    b_it, b_sc = G.topk_bf16(users, K)
+    out = {"users": int(len(users)),
+           "recall_bf16_vs_fp32": float(np.mean([len(set(a) & set(b)) / K for a, b in zip(f_it, b_it)]))}
+    Qd, bid = Q.astype(np.float64), bi.astype(np.float64)
+    rec = {"fp32": [], "bf16": []}
+    err = {"fp32": 0.0, "bf16": 0.0}
+    for row in range(min(n64, len(users))):
+        uu = users[row]
+        s64 = mu + float(bu[uu]) + bid + Qd @ P[uu].astype(np.float64)
+        best = set(np.argsort(-s64, kind="stable")[:K].tolist())
+        for name, its, scs in (("fp32", f_it[row], f_sc[row]), ("bf16", b_it[row], b_sc[row])):
+            rec[name].append(len(best & set(its.tolist())) / K)
+            err[name] = max(err[name], float(np.abs(scs.astype(np.float64) - s64[its]).max()))
+    for name in ("fp32", "bf16"):
+        out[f"recall_{name}_vs_fp64"] = float(np.mean(rec[name]))
+        out[f"max_score_error_{name}_vs_fp64"] = err[name]
+    out["fp64_users"] = min(n64, len(users))
+    return out
+
+
 def serving_leg(binding, args):
     """Top-100 serving on the 1M-user x 100k-item, k=128 factor tables:
     the continuous-batching server scoring in BF16 (FP32 rescoring) against
@@ -99,15 +124,28 @@ def serving_leg(binding, args):
     P, Q, bu, bi, mu = synth.serving_factors(sc.m, sc.n, sc.k, seed=args.seed + 3)
     G = binding.Model(sc.m, sc.n, sc.k, 1)
     G.set_factors(P, Q, bu, bi, mu)
-    del P, bu
     log(f"serving tables {sc.m} x {sc.n} x {sc.k} ready in {time.time() - t0:.1f}s")
+    # recall of BF16 scoring on these tables and on tables with a decaying
+    # spectrum (scale 1/sqrt(1+f) on factor f), the harder case for it
+    rrng = np.random.default_rng(args.seed + 14)
+    recall = {"iid": tables_recall(G, P, Q, bu, bi, mu, sc.K, rrng.integers(0, sc.m, 4096).astype(np.int32))}
+    del P, bu
+    P2, Q2, bu2, bi2, mu2 = synth.serving_factors(sc.m, sc.n, sc.k, seed=args.seed + 4, correlated=True)
+    G2 = binding.Model(sc.m, sc.n, sc.k, 1)
+    G2.set_factors(P2, Q2, bu2, bi2, mu2)
+    recall["decaying_spectrum"] = tables_recall(G2, P2, Q2, bu2, bi2, mu2, sc.K,
+                                                rrng.integers(0, sc.m, 4096).astype(np.int32))
+    G2.close()
+    del P2, Q2, bu2, bi2, G2
+    log("serving tables recall@100 BF16 vs FP32: " + ", ".join(
+        f"{name} {v['recall_bf16_vs_fp32']:.6f} (vs FP64 {v['recall_bf16_vs_fp64']:.4f})" for name, v in recall.items()))
     rng = np.random.default_rng(args.seed + 11)
     n = args.serving_requests
     reqs = serving.make_stream(rng, n, 0, sc.m, sc.n, Q, bi, mu, topk_frac=sc.topk_frac,
                                batch_range=sc.batch_range, foldin_range=sc.foldin_range)
     warm = serving.make_stream(rng, 8, 0, sc.m, sc.n, Q, bi, mu, topk_frac=sc.topk_frac,
                                batch_range=sc.batch_range, foldin_range=sc.foldin_range)
-    out = {"tables": f"{sc.m} x {sc.n}, k={sc.k}", "K": sc.K, "requests": n,
+    out = {"tables": f"{sc.m} x {sc.n}, k={sc.k}", "K": sc.K, "requests": n, "recall": recall,
            "mix": f"{int(sc.topk_frac * 100)}% top-{sc.K} for log-uniform {sc.batch_range} users, "
                   f"rest fold-in of log-uniform {sc.foldin_range} ratings"}
     users = sum(len(r.users) for r in reqs if r.kind == "topk")

@@ -13,7 +13,8 @@ against FP64 scores on sampled users) and in BF16 with FP32 rescoring
 
 Serving tables (1,000,000 x 100,000, k = 128): server results equal the
 direct BF16 calls, BF16 recall against FP32 of at least 0.99, epsilon-valid
-answers on sampled users.
+answers on sampled users.  The same tables with a decaying spectrum (factor
+f scaled by 1/sqrt(1 + f)): BF16 recall against FP32 of at least 0.99.
 
 Batched workload at 1/4 linear scale (the benchmark runs it at full size and
 checks four problems the same way): sampled problems equal the
@@ -142,6 +143,39 @@ def test_serving_tables_full_size():
     bs = np.concatenate([G.topk_bf16(users[pick], sc.K)[1]])
     eps_valid(bf[pick], bs, P, Q, bu, bi, mu, users[pick], sc.K, (sc.k + 8) * 2.0 ** -23)
     eps_valid(fi[pick], fs[pick], P, Q, bu, bi, mu, users[pick], sc.K, (sc.k + 8) * 2.0 ** -23)
+
+
+def test_serving_tables_decaying_spectrum():
+    """Serving-size tables (1,000,000 x 100,000, k = 128) whose factor f is
+    scaled by 1/sqrt(1 + f), the case with more near ties: BF16 recall@100
+    against FP32 is at least 0.99 over 4096 users; sampled FP32 answers are
+    epsilon-valid against FP64 scores, and the BF16 path's rescored scores
+    are within the same epsilon of the FP64 scores of the items it returns."""
+    from paper_1907_07410_amd import binding as B, synth
+    from test_gpu_parity import eps_valid
+    sc = configs.SERVING
+    P, Q, bu, bi, mu = synth.serving_factors(sc.m, sc.n, sc.k, seed=6, correlated=True)
+    G = B.Model(sc.m, sc.n, sc.k, 1)
+    G.set_factors(P, Q, bu, bi, mu)
+    rng = np.random.default_rng(22)
+    users = rng.integers(0, sc.m, 4096).astype(np.int32)
+    fi, fs = G.topk(users, sc.K)
+    bi_, bs = G.topk_bf16(users, sc.K)
+    recall = float(np.mean([len(set(a) & set(b)) / sc.K for a, b in zip(fi, bi_)]))
+    log("decaying-spectrum tables: bf16 recall@100 vs fp32 over", len(users), "users:", recall)
+    assert recall >= 0.99
+    pick = rng.choice(len(users), 16, replace=False)
+    eps_scale = (sc.k + 8) * 2.0 ** -23
+    eps_valid(fi[pick], fs[pick], P, Q, bu, bi, mu, users[pick], sc.K, eps_scale)
+    Qd = Q.astype(np.float64)
+    for row in pick:
+        u = users[row]
+        s64 = mu + float(bu[u]) + bi.astype(np.float64) + Qd @ P[u].astype(np.float64)
+        eps = eps_scale * (np.abs(Qd * P[u].astype(np.float64)).sum(axis=1) + np.abs(bi) + abs(mu + bu[u])).max()
+        it = bi_[row]
+        assert len(set(it.tolist())) == sc.K and np.all(np.diff(bs[row]) <= 0)
+        assert np.all(np.abs(bs[row] - s64[it]) <= eps)
+    G.close()
 
 
 def test_batched_quarter_scale_equals_alone():

@@ -378,6 +378,9 @@ bmf_status bmf_server_create(bmf_ctx *c, const bmf_server_config *cfg, bmf_serve
 /* Stops the scheduler (queued requests are dropped, running batches
  * finish) and frees the workspace. */
 void bmf_server_destroy(bmf_server *S);
+/* The server's last error message (a scheduler failure starts with
+ * "server failed: ").  The string is the calling thread's copy, valid until
+ * that thread's next call of this function. */
 const char *bmf_server_last_error(const bmf_server *S);
 /* Top-K for nu user ids (host array, copied); precision 0 = FP32 MFMA,
  * 1 = BF16 + FP32 rescore; 1 <= K <= 512.  *id names the request.

@@ -82,7 +82,7 @@ struct bmf_server {
     size_t part_bytes = 0;
     DevBuf arena;
     std::vector<Slot> slots;
-    std::mutex mu;
+    mutable std::mutex mu;
     std::condition_variable cv;
     std::deque<std::shared_ptr<Request>> queue;
     std::map<int64_t, std::shared_ptr<Request>> live;
@@ -397,11 +397,11 @@ void scheduler(bmf_server *S) {
         }
     } catch (const Error &e) {
         S->failed = true;
-        S->err = e.msg;
+        S->err = "server failed: " + e.msg;
         S->ctx->poisoned = e.code == BMF_E_DEVICE;
     } catch (...) {
         S->failed = true;
-        S->err = "unexpected exception in the serving scheduler";
+        S->err = "server failed: unexpected exception in the serving scheduler";
     }
     S->cv.notify_all();
 }
@@ -439,7 +439,7 @@ bmf_status submit(bmf_server *S, std::shared_ptr<Request> r, int64_t *id) {
                 BMF_FAIL(BMF_E_RANGE, "fold-in rating out of range");
         const size_t need = request_bytes(M, *r, S->cfg.Kc);
         std::lock_guard<std::mutex> lk(S->mu);
-        if (S->failed) BMF_FAIL(BMF_E_DEVICE, "server failed: " + S->err);
+        if (S->failed) BMF_FAIL(BMF_E_DEVICE, S->err);
         if (need > S->part_bytes || request_host_in(*r) + 4096 > S->part_bytes ||
             request_host_out(*r, M.k) + 4096 > S->part_bytes) {
             S->rejected += 1;
@@ -534,7 +534,14 @@ void bmf_server_destroy(bmf_server *S) {
     delete S;
 }
 
-const char *bmf_server_last_error(const bmf_server *S) { return S ? S->err.c_str() : ""; }
+const char *bmf_server_last_error(const bmf_server *S) {
+    // a copy per calling thread: the scheduler thread may set the message
+    thread_local std::string msg;
+    if (!S) return "";
+    std::lock_guard<std::mutex> lk(S->mu);
+    msg = S->err;
+    return msg.c_str();
+}
 
 bmf_status bmf_server_submit_topk(bmf_server *S, const int32_t *users, int32_t nu, int32_t K, int32_t precision,
                                   int64_t *id) {
@@ -572,11 +579,7 @@ bmf_status bmf_server_poll(bmf_server *S, int64_t id, int32_t wait, int32_t *don
         S->cv.wait(lk, [&] { return r->done || S->failed; });
     if (!r->done) {
         *done = 0;
-        if (S->failed) {
-            S->err = "server failed: " + S->err;
-            return BMF_E_DEVICE;
-        }
-        return BMF_OK;
+        return S->failed ? BMF_E_DEVICE : BMF_OK;  // the scheduler's message stays in err
     }
     *done = 1;
     if (items_out) std::memcpy(items_out, r->out_items.data(), r->out_items.size() * 4);

@@ -44,6 +44,7 @@ def test_create_rejects_bad_sizes_without_touching_the_device(binding):
         assert st == binding.BMF_E_INVAL
         assert h.value is None
         assert binding.lib.bmf_last_error(None)
+        assert binding.lib.bmf_server_last_error(None) == b""
     assert binding.lib.bmf_create(5, 5, 4, 2, None) == binding.BMF_E_INVAL
 
 

@@ -29,6 +29,15 @@
 
 using namespace bmf;
 
+namespace {
+// A problem's ratings on the device, validated, kept until its grid is
+// chosen and its context loaded.
+struct Loaded {
+    DevBuf u, i, r;
+    int64_t nnz = 0;
+};
+}  // namespace
+
 struct bmf_batch {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -45,6 +54,7 @@ struct bmf_batch {
     bool poisoned = false;
     std::string err;
     DevBuf d_probs, d_items;
+    std::vector<std::unique_ptr<Loaded>> staged;  // per problem, until tuned
 };
 
 namespace {
@@ -176,11 +186,6 @@ std::vector<Candidate> candidates(int64_t m, int64_t n, int k, const int32_t *du
     return out;
 }
 
-struct Loaded {
-    DevBuf u, i, r;
-    int64_t nnz = 0;
-};
-
 template <class F>
 bmf_status guarded_batch(bmf_batch *B, F &&f) {
     if (!B) return BMF_E_INVAL;
@@ -206,16 +211,9 @@ bmf_status guarded_batch(bmf_batch *B, F &&f) {
     }
 }
 
-std::map<bmf_batch *, std::vector<std::unique_ptr<Loaded>>> g_staged;  // COO kept until tuned
-std::mutex g_staged_mu;
-
 void tune_and_load(bmf_batch *B) {
     // problems whose context does not exist yet: choose grids, then load
-    std::vector<std::unique_ptr<Loaded>> *staged;
-    {
-        std::lock_guard<std::mutex> lk(g_staged_mu);
-        staged = &g_staged[B];
-    }
+    std::vector<std::unique_ptr<Loaded>> *staged = &B->staged;
     const int np = (int)B->m.size();
     std::vector<int> todo;
     for (int p = 0; p < np; ++p)
@@ -350,10 +348,7 @@ bmf_status bmf_batch_create(int32_t nprob, const int64_t *m, const int64_t *n, i
     if (b) B->b_req.assign(b, b + nprob);
     B->probs.assign(nprob, nullptr);
     B->predicted_ms.assign(nprob, -1.0);
-    {
-        std::lock_guard<std::mutex> lk(g_staged_mu);
-        g_staged[B].resize(nprob);
-    }
+    B->staged.resize(nprob);
     *out = B;
     return BMF_OK;
 }
@@ -362,10 +357,7 @@ void bmf_batch_destroy(bmf_batch *B) {
     if (!B) return;
     (void)hipSetDevice(B->device);
     for (auto *c : B->probs) bmf_destroy(c);
-    {
-        std::lock_guard<std::mutex> lk(g_staged_mu);
-        g_staged.erase(B);
-    }
+    B->staged.clear();
     if (B->stream) {
         (void)hipStreamSynchronize(B->stream);
         (void)hipStreamDestroy(B->stream);
@@ -415,8 +407,7 @@ bmf_status bmf_batch_load(bmf_batch *B, int32_t p, const int32_t *u, const int32
                                          B->n[p], scratch, B->stream);
         if (bad >= 0) BMF_FAIL(BMF_E_RANGE, "problem " + std::to_string(p) + ": rating " + std::to_string(bad) +
                                                 " is out of range or not finite");
-        std::lock_guard<std::mutex> lk(g_staged_mu);
-        g_staged[B][p] = std::move(L);
+        B->staged[p] = std::move(L);
     });
 }
 
@@ -474,9 +465,17 @@ bmf_status bmf_batch_epochs(bmf_batch *B, int32_t epochs, const float hp[8]) {
         // the factor tables are touched by the batch stream only after the
         // problems' own streams are idle
         for (int p = 0; p < np; ++p) BMF_HIP(hipStreamSynchronize(B->probs[p]->M.stream));
-        hipEvent_t e0, e1;
-        BMF_HIP(hipEventCreate(&e0));
-        BMF_HIP(hipEventCreate(&e1));
+        // timing events, destroyed on every way out
+        struct Events {
+            hipEvent_t a = nullptr, b = nullptr;
+            ~Events() {
+                if (a) (void)hipEventDestroy(a);
+                if (b) (void)hipEventDestroy(b);
+            }
+        } ev;
+        BMF_HIP(hipEventCreate(&ev.a));
+        BMF_HIP(hipEventCreate(&ev.b));
+        const hipEvent_t e0 = ev.a, e1 = ev.b;
         BMF_HIP(hipEventRecord(e0, B->stream));
         const HP h{hp[0], hp[1], hp[2], hp[3], hp[4], hp[5], hp[6], hp[7]};
         for (int64_t t = 0; t < maxT; ++t)
@@ -486,8 +485,6 @@ bmf_status bmf_batch_epochs(bmf_batch *B, int32_t epochs, const float hp[8]) {
         BMF_HIP(hipStreamSynchronize(B->stream));
         float ms = 0;
         BMF_HIP(hipEventElapsedTime(&ms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
         B->ms += ms;
         B->launches += maxT;
         for (int p = 0; p < np; ++p) {

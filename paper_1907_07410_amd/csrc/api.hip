@@ -64,15 +64,17 @@ void check_finite_hp(const float *hp) {
 // of nnz ratings for M's sizes, and make it the training set with mean mu.
 // The buffers are taken over.
 void set_training(Model &M, DevBuf &du, DevBuf &di, DevBuf &dr, int64_t nnz, double mu) {
-    if (M.ooc.on) {  // kernels may still read its device buffers
-        BMF_HIP(hipStreamSynchronize(M.stream));
-        M.ooc.release();
-    }
     Partition P;
     build_partition(P, du.as<int32_t>(), di.as<int32_t>(), dr.as<float>(), nnz, M.m, M.n, M.b, M.stream);
     Plan plan;  // built now when an epoch will use it, else on first demand
     if (M.sgd_kernel == 2 || (M.sgd_kernel == 0 && plan_pays(P.nnz, M.b)))
         build_plan(plan, P, M.b, M.k, sgd_max_lds(M.device), M.stream);
+    // a failure above leaves the model as it was; below, only a device error
+    // (which poisons the context) can interrupt
+    if (M.ooc.on) {  // kernels may still read its device buffers
+        BMF_HIP(hipStreamSynchronize(M.stream));
+        M.ooc.release();
+    }
     M.cu.swap(du);
     M.ci.swap(di);
     M.cr.swap(dr);

@@ -103,6 +103,41 @@ def test_partition_and_schedule_bit_exact(B, orc, name, m, n, b, spec):
     assert mu == pytest.approx(orc.mean(rat.r), rel=1e-13)
 
 
+def test_wide_blocks_and_the_local_index_limit(B, orc):
+    """Blocks wider than 65,536 columns (17-bit local column ids): partition
+    bit-exact and two epochs within 1e-4 of the oracle.  A grid whose local
+    (row, column) ids need more than 32 bits is refused at load with
+    BMF_E_RANGE and leaves the model unloaded; a finer grid of the same
+    data (16 + 16 bits) loads, partitions exactly and trains like the
+    oracle."""
+    m, n = 40, 150000
+    rat = synth.random_coo(m, n, 4000, seed=17, dup=True)
+    G, O = make_pair(B, orc, m, n, 16, 2, rat)
+    bp, perm = G.get_partition(len(rat))
+    obp, operm = orc.partition(m, n, 2, rat.u, rat.i)
+    assert np.array_equal(bp, obp) and np.array_equal(perm, operm)
+    for _ in range(2):
+        G.epoch(0.01, 0.02)
+        O.epoch(0.01, 0.02)
+    assert max_abs_diff(G, O) <= 1e-4
+    m = n = 200000
+    big = synth.random_coo(m, n, 1000, seed=3, dup=True)
+    H = B.Model(m, n, 8, 1)
+    with pytest.raises(B.BmfError) as ex:
+        H.load_ratings(big.u, big.i, big.r)
+    assert ex.value.status == B.BMF_E_RANGE
+    with pytest.raises(B.BmfError) as ex:
+        H.epoch(0.01, 0.02)
+    assert ex.value.status == B.BMF_E_STATE
+    G, O = make_pair(B, orc, m, n, 8, 4, big)
+    bp, perm = G.get_partition(len(big))
+    obp, operm = orc.partition(m, n, 4, big.u, big.i)
+    assert np.array_equal(bp, obp) and np.array_equal(perm, operm)
+    G.epoch(0.01, 0.02)
+    O.epoch(0.01, 0.02)
+    assert max_abs_diff(G, O) <= 1e-4
+
+
 def test_empty_load_and_epoch(B):
     G = B.Model(10, 10, 4, 2)
     G.load_ratings(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))

@@ -198,10 +198,12 @@ def test_kernels_bit_identical_and_close_to_oracle(B, orc, k, b, m, n, nnz, dup)
     assert d <= 1e-4
 
 
-def test_large_k_uses_reference_kernel(B, orc):
-    # k > 128: no plan; the automatic choice runs the 64-lane reference kernel
+@pytest.mark.parametrize("k", [200, 1024])
+def test_large_k_uses_reference_kernel(B, orc, k):
+    # k > 128: no plan; the automatic choice runs the 64-lane reference
+    # kernel (k = 1024 is the largest k a model accepts)
     rat = synth.random_coo(150, 90, 3000, seed=5, dup=True)
-    G, O = make_pair(B, orc, 150, 90, 200, 3, rat, kernel=0)
+    G, O = make_pair(B, orc, 150, 90, k, 3, rat, kernel=0)
     with pytest.raises(B.BmfError) as ex:
         G.set_option(B.OPT_SGD_KERNEL, 2)
         G.epoch(0.01, 0.02)
@@ -307,7 +309,8 @@ def eps_valid(items, scores, P, Q, bu, bi, mu, users, K, eps_scale):
 
 
 @pytest.mark.parametrize("k,n,nu,K", [(16, 500, 40, 10), (64, 3000, 5, 100), (128, 17800, 37, 100),
-                                      (13, 1000, 20, 50), (64, 4000, 1, 300)])
+                                      (13, 1000, 20, 50), (64, 4000, 1, 300), (200, 2500, 9, 64),
+                                      (256, 6000, 17, 100)])
 def test_topk_fp32_eps_valid(B, orc, k, n, nu, K):
     rng = np.random.default_rng(k + n)
     m = 200
@@ -352,9 +355,10 @@ def test_topk_batch_invariance(B):
         assert np.array_equal(one_s[0].view(np.uint32), big_s[q].view(np.uint32))
 
 
-def test_topk_bf16_recall_and_rescore(B, orc):
+@pytest.mark.parametrize("k", [128, 200, 256])
+def test_topk_bf16_recall_and_rescore(B, orc, k):
     rng = np.random.default_rng(11)
-    m, n, k, K = 256, 17800, 128, 100
+    m, n, K = 256, 17800, 100
     P = rng.normal(0, 0.3, (m, k)).astype(np.float32)
     Q = rng.normal(0, 0.3, (n, k)).astype(np.float32)
     bu = rng.normal(0, 0.3, m).astype(np.float32)
@@ -371,7 +375,7 @@ def test_topk_bf16_recall_and_rescore(B, orc):
 
 
 # ---------------------------------------------------------------- fold-in
-@pytest.mark.parametrize("k,nr", [(128, 5), (128, 500), (64, 37), (13, 100)])
+@pytest.mark.parametrize("k,nr", [(128, 5), (128, 500), (64, 37), (13, 100), (256, 300), (1000, 60)])
 def test_foldin_matches_oracle(B, orc, k, nr):
     rng = np.random.default_rng(k + nr)
     n = 2000

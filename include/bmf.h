@@ -97,7 +97,14 @@ typedef enum {
      * host in input order.  Such a load takes host arrays only
      * (bmf_load_ratings), fixes the SGD kernel (set BMF_OPT_SGD_KERNEL before
      * it), and bmf_add_ratings refuses the context.  0 (default): resident. */
-    BMF_OPT_OUT_OF_CORE = 7
+    BMF_OPT_OUT_OF_CORE = 7,
+    /* The epoch counter: the index of the next epoch (0 <= value < 2^31),
+     * which picks its stratum order in mode 1 (BMF_OPT_STRATUM_ORDER).  With
+     * factors saved by bmf_get_factors after e epochs and restored by
+     * bmf_set_factors into a context loaded with the same ratings, setting
+     * it to e makes the following epochs those of the uninterrupted run
+     * (Algorithm 1's loop resumed at iteration e). */
+    BMF_OPT_EPOCH = 8
 } bmf_option;
 
 /* ------------------------------------------------------------- lifetime */

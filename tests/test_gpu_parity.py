@@ -138,6 +138,44 @@ def test_wide_blocks_and_the_local_index_limit(B, orc):
     assert max_abs_diff(G, O) <= 1e-4
 
 
+def test_resume_from_saved_factors_is_exact(B):
+    """Checkpoint and resume: Algorithm 1's loop stopped after two
+    iterations and restarted in a new context (other initial seed) from the
+    returned factors and the epoch counter continues exactly as the
+    uninterrupted run, with the seeded stratum order; without the counter
+    the strata come in another order and the factors differ."""
+    rat = synth.random_coo(500, 300, 20000, seed=9, dup=True)
+
+    def fresh(seed):
+        G = B.Model(500, 300, 32, 8, seed=seed, order_mode=1, order_seed=44)
+        G.load_ratings(rat.u, rat.i, rat.r)
+        return G
+
+    A = fresh(1001)
+    for _ in range(5):
+        A.epoch(0.01, 0.02)
+    S = fresh(1001)
+    for _ in range(2):
+        S.epoch(0.01, 0.02)
+    ck = S.get_factors()
+    R = fresh(7)
+    R.set_factors(*ck)
+    R.set_option(B.OPT_EPOCH, 2)
+    assert R.epoch_count() == 2
+    for _ in range(3):
+        R.epoch(0.01, 0.02)
+    a, r = A.get_factors(), R.get_factors()
+    assert all(np.array_equal(x.view(np.uint32), y.view(np.uint32)) for x, y in zip(a[:4], r[:4]))
+    W = fresh(7)
+    W.set_factors(*ck)
+    for _ in range(3):
+        W.epoch(0.01, 0.02)
+    assert not np.array_equal(W.get_factors()[0], a[0])
+    with pytest.raises(B.BmfError) as ex:
+        R.set_option(B.OPT_EPOCH, -1)
+    assert ex.value.status == B.BMF_E_INVAL and R.epoch_count() == 5
+
+
 def test_empty_load_and_epoch(B):
     G = B.Model(10, 10, 4, 2)
     G.load_ratings(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32))

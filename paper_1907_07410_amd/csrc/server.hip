@@ -9,9 +9,11 @@
 // fits the partition (admission by memory) and the row cap allows, and
 // enqueues it on the slot's stream: uploads, fold-in kernel for the batch's
 // new users, user-row gather, one scoring pass per precision over all rows
-// of the batch, downloads, completion event.  Requests that arrive while
-// batches are on the GPU go into the next batch; batches on different
-// slots overlap on the device.  Every row is scored on its own (the MFMA
+// of the batch, downloads, completion event.  When the event has fired, a
+// completion thread copies the results out of the slot's pinned staging and
+// frees the slot, so the scheduler goes on launching meanwhile.  Requests
+// that arrive while batches are on the GPU go into the next batch; batches
+// on different slots overlap on the device.  Every row is scored on its own (the MFMA
 // latent order is fixed and the selection is exact with a fixed tie rule),
 // so a request's result does not depend on the batch it lands in.
 #include <algorithm>
@@ -40,8 +42,11 @@ struct Request {
     std::vector<float> ratings;
     Clock::time_point t_submit, t_done;
     bool done = false;
-    std::vector<int32_t> out_items;
-    std::vector<float> out_scores, out_p;
+    // results, written once by a completion thread (no zero fill first)
+    std::unique_ptr<int32_t[]> out_items;
+    std::unique_ptr<float[]> out_scores;
+    size_t out_n = 0;
+    std::vector<float> out_p;
     float out_bu = 0.f;
     size_t bytes = 0;
 };
@@ -67,7 +72,8 @@ struct Slot {
     unsigned char *dev = nullptr;   // partition of the device workspace
     unsigned char *hin = nullptr;   // pinned staging for inputs
     unsigned char *hout = nullptr;  // pinned staging for outputs
-    bool busy = false;
+    bool busy = false;       // a batch is in flight or its results are being copied out
+    bool finishing = false;  // handed to a completion thread
     std::vector<Placement> placed;
     Group g[2];
     size_t host_off_out[2] = {0, 0};
@@ -90,6 +96,12 @@ struct bmf_server {
     bool stop = false, failed = false;
     std::string err;
     std::thread worker;
+    // completion threads: copy finished batches' results out of the pinned
+    // staging while the scheduler keeps launching
+    std::vector<std::thread> finishers;
+    std::deque<int> finished;  // slots whose batch completed on the device
+    std::condition_variable fcv;
+    bool finishers_stop = false;
     // statistics
     int64_t submitted = 0, completed = 0, rejected = 0, batches = 0, rows = 0;
     size_t bytes_in_use = 0, peak_bytes = 0;
@@ -250,9 +262,11 @@ void launch_batch(bmf_server *S, Slot &sl) {
     BMF_HIP(hipEventRecord(sl.done, sl.stream));
 }
 
-void finish_batch(bmf_server *S, Slot &sl) {
+// Copies a completed batch's results from the slot's pinned staging into
+// its requests (no lock: until published, the slot and its requests are the
+// caller's alone).
+void copy_results(bmf_server *S, Slot &sl) {
     const int k = S->ctx->M.k;
-    const auto now = Clock::now();
     for (int g = 0; g < 2; ++g) {
         Group &G = sl.g[g];
         const int64_t rows = G.nusers + G.nfold;
@@ -267,27 +281,69 @@ void finish_batch(bmf_server *S, Slot &sl) {
             if (pl.group != g) continue;
             Request &r = *pl.req;
             const int64_t nrow = r.foldin ? 1 : (int64_t)r.users.size();
-            r.out_items.resize(nrow * r.K);
-            r.out_scores.resize(nrow * r.K);
-            for (int64_t q = 0; q < nrow; ++q) {
-                std::memcpy(&r.out_items[q * r.K], it + (pl.row + q) * G.K, r.K * 4);
-                std::memcpy(&r.out_scores[q * r.K], sc + (pl.row + q) * G.K, r.K * 4);
+            r.out_n = (size_t)nrow * r.K;
+            r.out_items.reset(new int32_t[r.out_n]);
+            r.out_scores.reset(new float[r.out_n]);
+            if (r.K == G.K) {
+                std::memcpy(r.out_items.get(), it + pl.row * G.K, r.out_n * 4);
+                std::memcpy(r.out_scores.get(), sc + pl.row * G.K, r.out_n * 4);
+            } else {
+                for (int64_t q = 0; q < nrow; ++q) {
+                    std::memcpy(&r.out_items[q * r.K], it + (pl.row + q) * G.K, r.K * 4);
+                    std::memcpy(&r.out_scores[q * r.K], sc + (pl.row + q) * G.K, r.K * 4);
+                }
             }
             if (r.foldin) {
                 const int64_t fidx = pl.row - G.nusers;
                 r.out_p.assign(pv + fidx * G.plan.kp, pv + fidx * G.plan.kp + k);
                 r.out_bu = bv[fidx];
             }
-            r.t_done = now;
-            r.done = true;
-            S->completed += 1;
-            S->lat_ms.push_back(std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count());
         }
+    }
+}
+
+// Marks a copied batch's requests done and frees its slot (lock held).
+void publish_batch(bmf_server *S, Slot &sl) {
+    const auto now = Clock::now();
+    for (auto &pl : sl.placed) {
+        Request &r = *pl.req;
+        r.t_done = now;
+        r.done = true;
+        S->completed += 1;
+        S->lat_ms.push_back(std::chrono::duration<double, std::milli>(r.t_done - r.t_submit).count());
     }
     S->bytes_in_use -= sl.bytes;
     sl.bytes = 0;
     sl.placed.clear();
+    sl.finishing = false;
     sl.busy = false;
+}
+
+void finisher(bmf_server *S) {
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (true) {
+        S->fcv.wait(lk, [&] { return S->finishers_stop || !S->finished.empty(); });
+        if (S->finished.empty()) break;  // stop, nothing left
+        Slot &sl = S->slots[S->finished.front()];
+        S->finished.pop_front();
+        bool ok = true;
+        {
+            lk.unlock();
+            try {
+                copy_results(S, sl);
+            } catch (...) {
+                ok = false;
+            }
+            lk.lock();
+        }
+        if (ok) {
+            publish_batch(S, sl);
+        } else {
+            S->failed = true;
+            S->err = "server failed: host allocation for results failed";
+        }
+        S->cv.notify_all();
+    }
 }
 
 // Releases a held lock for a scope and takes it back on exit (also when an
@@ -306,17 +362,19 @@ void scheduler(bmf_server *S) {
         while (true) {
             bool progressed = false;
             // completions
-            for (auto &sl : S->slots) {
-                if (!sl.busy) continue;
-                const hipError_t q = hipEventQuery(sl.done);
-                if (q == hipSuccess) {
-                    finish_batch(S, sl);
+            for (size_t q = 0; q < S->slots.size(); ++q) {
+                Slot &sl = S->slots[q];
+                if (!sl.busy || sl.finishing) continue;
+                const hipError_t e = hipEventQuery(sl.done);
+                if (e == hipSuccess) {
+                    sl.finishing = true;
+                    S->finished.push_back((int)q);
                     progressed = true;
-                } else if (q != hipErrorNotReady) {
-                    BMF_HIP(q);
+                } else if (e != hipErrorNotReady) {
+                    BMF_HIP(e);
                 }
             }
-            if (progressed) S->cv.notify_all();
+            if (progressed) S->fcv.notify_all();
             // new batches
             for (auto &sl : S->slots) {
                 if (sl.busy || S->queue.empty()) continue;
@@ -507,6 +565,7 @@ bmf_status bmf_server_create(bmf_ctx *c, const bmf_server_config *cfg, bmf_serve
         return e.code;
     }
     bmf_server *raw = S.release();
+    for (int q = 0; q < 2; ++q) raw->finishers.emplace_back(finisher, raw);
     raw->worker = std::thread(scheduler, raw);
     *out = raw;
     return BMF_OK;
@@ -521,6 +580,14 @@ void bmf_server_destroy(bmf_server *S) {
     }
     S->cv.notify_all();
     if (S->worker.joinable()) S->worker.join();
+    {
+        // the scheduler has handed over every completed batch
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->finishers_stop = true;
+    }
+    S->fcv.notify_all();
+    for (auto &t : S->finishers)
+        if (t.joinable()) t.join();
     (void)hipSetDevice(S->ctx->M.device);
     for (auto &sl : S->slots) {
         if (sl.stream) {
@@ -582,8 +649,8 @@ bmf_status bmf_server_poll(bmf_server *S, int64_t id, int32_t wait, int32_t *don
         return S->failed ? BMF_E_DEVICE : BMF_OK;  // the scheduler's message stays in err
     }
     *done = 1;
-    if (items_out) std::memcpy(items_out, r->out_items.data(), r->out_items.size() * 4);
-    if (scores_out) std::memcpy(scores_out, r->out_scores.data(), r->out_scores.size() * 4);
+    if (items_out) std::memcpy(items_out, r->out_items.get(), r->out_n * 4);
+    if (scores_out) std::memcpy(scores_out, r->out_scores.get(), r->out_n * 4);
     if (p_out && r->foldin) std::memcpy(p_out, r->out_p.data(), r->out_p.size() * 4);
     if (bu_out && r->foldin) *bu_out = r->out_bu;
     if (latency_ns)

@@ -151,3 +151,52 @@ def test_drain_waits_for_every_request(B, model):
         for rid in ids:
             assert S.poll(rid, wait=False) is not None, (rep, rid)
     S.close()
+
+
+def test_concurrent_clients_get_their_own_results(B, model):
+    """Four client threads submit and poll at the same time (polls in
+    reverse order, mixed precisions and fold-ins): every result equals the
+    direct call for the same request, bit for bit, while the scheduler and
+    the completion threads run batches of everyone's requests."""
+    import threading
+    G, (P, Q, bu, bi, mu) = model
+    S = B.Server(G)
+    rngs = [np.random.default_rng(100 + t) for t in range(4)]
+    streams = [serving.make_stream(rngs[t], 30, 0, G.m, G.n, Q, bi, mu, batch_range=(1, 400)) for t in range(4)]
+    results = [None] * 4
+    errors = []
+
+    def client(t):
+        try:
+            ids = []
+            for q, r in enumerate(streams[t]):
+                prec = (q + t) % 2
+                if r.kind == "topk":
+                    ids.append((S.submit_topk(r.users, 100, prec), r, prec))
+                else:
+                    ids.append((S.submit_foldin(r.items, r.ratings, 100, prec), r, prec))
+            results[t] = [(S.poll(rid, wait=True), r, prec) for rid, r, prec in reversed(ids)]
+        except Exception as e:  # reported by the main thread
+            errors.append(e)
+
+    threads = [threading.Thread(target=client, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=60)
+    assert not errors and all(not th.is_alive() for th in threads)
+    n = 0
+    for t in range(4):
+        for res, r, prec in results[t]:
+            if r.kind == "topk":
+                di, ds = (G.topk_bf16 if prec else G.topk)(r.users, 100)
+                assert np.array_equal(res["items"], di)
+                assert np.array_equal(res["scores"].view(np.uint32), ds.view(np.uint32))
+            else:
+                p, b_ = G.foldin(r.items, r.ratings, 10, 0.005, 0.05)
+                assert np.array_equal(res["p"].view(np.uint32), p.view(np.uint32)) and res["bu"] == b_
+            n += 1
+    st = S.stats()
+    log("concurrent clients", n, "requests in", st["batches"], "batches")
+    assert n == 120 and st["completed"] == 120
+    S.close()

@@ -62,8 +62,7 @@ struct Group {
     int64_t nusers = 0, nfold = 0, fold_ratings = 0;
     int K = 0, max_nr = 0;
     TopkPlan plan;
-    size_t off_users = 0, off_fitems = 0, off_fr = 0, off_foff = 0, off_buf = 0, off_work = 0, off_items = 0,
-           off_scores = 0, total = 0;
+    size_t off_in = 0, off_buf = 0, off_work = 0, off_items = 0, off_scores = 0, total = 0;
 };
 
 struct Slot {
@@ -181,14 +180,15 @@ void launch_batch(bmf_server *S, Slot &sl) {
             o += align256(b);
             return at;
         };
-        G.off_users = take(std::max<int64_t>(G.nusers, 1) * 4);
-        G.off_fitems = take(std::max<int64_t>(G.fold_ratings, 1) * 4);
-        G.off_fr = take(std::max<int64_t>(G.fold_ratings, 1) * 4);
-        G.off_foff = take((G.nfold + 1) * 8);
+        // inputs laid out as in the pinned staging, so one copy moves them:
+        // users | fold-in items | ratings, then (256-byte aligned) offsets
+        const size_t in_lists = align256((size_t)(G.nusers + 2 * G.fold_ratings) * 4);
+        const size_t in_bytes = in_lists + (size_t)(G.nfold + 1) * 8;
+        G.off_in = take(in_bytes);
         G.off_buf = take(std::max<int64_t>(G.nfold, 1) * 4);
         G.off_work = take(G.plan.total);
         G.off_items = take((size_t)rows * G.K * 4);
-        G.off_scores = take((size_t)rows * G.K * 4);
+        G.off_scores = take((size_t)rows * G.K * 4);  // right after the items, as in the staging
         if (o > S->part_bytes) BMF_FAIL(BMF_E_DEVICE, "internal: batch workspace exceeds its partition");
         dev_off = o;
         // host inputs: users | fold-in items | ratings | offsets, one copy
@@ -196,8 +196,7 @@ void launch_batch(bmf_server *S, Slot &sl) {
         int32_t *hu = reinterpret_cast<int32_t *>(h);
         int32_t *hi = hu + G.nusers;
         float *hr = reinterpret_cast<float *>(hi + G.fold_ratings);
-        int64_t *hoff = reinterpret_cast<int64_t *>(align256((size_t)(hr + G.fold_ratings) - (size_t)sl.hin) +
-                                                    sl.hin);
+        int64_t *hoff = reinterpret_cast<int64_t *>(h + in_lists);  // hin_off is a multiple of 256
         int64_t fo = 0, fi = 0;
         for (auto &pl : sl.placed) {
             if (pl.group != g) continue;
@@ -214,13 +213,13 @@ void launch_batch(bmf_server *S, Slot &sl) {
         hoff[fi] = fo;
         unsigned char *d = sl.dev;
         const hipStream_t st = sl.stream;
-        if (G.nusers) BMF_HIP(hipMemcpyAsync(d + G.off_users, hu, G.nusers * 4, hipMemcpyHostToDevice, st));
-        if (G.nfold) {
-            BMF_HIP(hipMemcpyAsync(d + G.off_fitems, hi, G.fold_ratings * 4, hipMemcpyHostToDevice, st));
-            BMF_HIP(hipMemcpyAsync(d + G.off_fr, hr, G.fold_ratings * 4, hipMemcpyHostToDevice, st));
-            BMF_HIP(hipMemcpyAsync(d + G.off_foff, hoff, (G.nfold + 1) * 8, hipMemcpyHostToDevice, st));
-        }
-        hin_off = align256((size_t)(hoff + G.nfold + 1) - (size_t)sl.hin);
+        unsigned char *din = d + G.off_in;
+        BMF_HIP(hipMemcpyAsync(din, h, in_bytes, hipMemcpyHostToDevice, st));
+        const int32_t *d_users = reinterpret_cast<const int32_t *>(din);
+        const int32_t *d_fitems = d_users + G.nusers;
+        const float *d_fr = reinterpret_cast<const float *>(d_fitems + G.fold_ratings);
+        const int64_t *d_foff = reinterpret_cast<const int64_t *>(din + in_lists);
+        hin_off += align256(in_bytes);
         // user rows: gather (rows past nusers become zero rows), then the
         // folded-in users overwrite their rows
         unsigned char *work = d + G.off_work;
@@ -229,7 +228,7 @@ void launch_batch(bmf_server *S, Slot &sl) {
             // (folded-in users, padding) starts as a zero row
             TopkPlan P2 = G.plan;
             P2.nu = G.nusers;
-            topk_gather(M, P2, reinterpret_cast<const int32_t *>(d + G.off_users), work, st);
+            topk_gather(M, P2, d_users, work, st);
         }
         if (G.nfold) {
             const HP hp{S->cfg.foldin_lr, S->cfg.foldin_reg, 0.f, 0.f, S->cfg.foldin_lr, S->cfg.foldin_reg, 0.f, 0.f};
@@ -237,20 +236,21 @@ void launch_batch(bmf_server *S, Slot &sl) {
             uint16_t *Ugb = g == 1 ? reinterpret_cast<uint16_t *>(work + G.plan.off_ugb) + G.nusers * G.plan.kb : nullptr;
             float *ub = reinterpret_cast<float *>(work + G.plan.off_ub) + G.nusers;
             float *bu_f = reinterpret_cast<float *>(d + G.off_buf);
-            foldin_launch(M, reinterpret_cast<const int32_t *>(d + G.off_fitems),
-                          reinterpret_cast<const float *>(d + G.off_fr), reinterpret_cast<const int64_t *>(d + G.off_foff),
-                          G.nfold, G.max_nr, S->cfg.foldin_passes, hp, Ug, G.plan.kp, bu_f, st);
+            foldin_launch(M, d_fitems, d_fr, d_foff, G.nfold, G.max_nr, S->cfg.foldin_passes, hp, Ug, G.plan.kp,
+                          bu_f, st);
             foldin_rows(bu_f, G.nfold, (float)M.mu, k, G.plan.kp, G.plan.kb, Ug, Ugb, ub, st);
         }
         int32_t *ditems = reinterpret_cast<int32_t *>(d + G.off_items);
         float *dscores = reinterpret_cast<float *>(d + G.off_scores);
         topk_score(M, G.plan, work, ditems, dscores, st);
-        // outputs
+        // outputs: items and scores (adjacent on both sides) in one copy
         sl.host_off_out[g] = hout_off;
-        BMF_HIP(hipMemcpyAsync(sl.hout + hout_off, ditems, (size_t)rows * G.K * 4, hipMemcpyDeviceToHost, st));
-        hout_off += align256((size_t)rows * G.K * 4);
-        BMF_HIP(hipMemcpyAsync(sl.hout + hout_off, dscores, (size_t)rows * G.K * 4, hipMemcpyDeviceToHost, st));
-        hout_off += align256((size_t)rows * G.K * 4);
+        const size_t list_bytes = align256((size_t)rows * G.K * 4);
+        if (G.off_scores != G.off_items + list_bytes)
+            BMF_FAIL(BMF_E_DEVICE, "internal: result lists are not adjacent in the workspace");
+        BMF_HIP(hipMemcpyAsync(sl.hout + hout_off, ditems, list_bytes + (size_t)rows * G.K * 4, hipMemcpyDeviceToHost,
+                               st));
+        hout_off += 2 * list_bytes;
         if (G.nfold) {
             BMF_HIP(hipMemcpyAsync(sl.hout + hout_off, work + G.plan.off_ug + (size_t)G.nusers * G.plan.kp * 4,
                                    (size_t)G.nfold * G.plan.kp * 4, hipMemcpyDeviceToHost, st));

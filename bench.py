@@ -32,8 +32,8 @@ MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}  # MI355X dense matrix peaks
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors
 # that make the counters match a plain 256 MiB copy kernel), valid for the
 # kernel sources with this sha1; reported as null once they change.
-SGD_TRAFFIC = {"sources_sha1": "2e80137064a3985836ab971c3d203e17446b556b",
-               "fetch_bytes": 26925544.3, "write_bytes": 21915903.3}
+SGD_TRAFFIC = {"sources_sha1": "0932b6019bd9bef949ea938a91afc3e27e113862",
+               "fetch_bytes": 26925611.8, "write_bytes": 21915844.7}
 SGD_SOURCES = ["paper_1907_07410_amd/csrc/sgd.hip", "paper_1907_07410_amd/csrc/plan.hip",
                "paper_1907_07410_amd/csrc/plan.h", "paper_1907_07410_amd/csrc/wave.h"]
 
@@ -280,13 +280,16 @@ def paper_leg(binding, args):
     from paper_1907_07410_amd import configs
     c = configs.PAPER_ML1M
     seeds = (args.seed, args.seed + 1, args.seed + 2)
-    runs = {"gpu_b8": [], "gpu_b3072": [], "gpu_b1": [], "oracle_b8": [], "oracle_b1": []}
+    runs = {"gpu_b8": [], "gpu_b3072": [], "gpu_b3072_graph": [], "gpu_b1": [], "oracle_b8": [], "oracle_b1": []}
     threads = max(1, min(len(os.sched_getaffinity(0)), 8))
     for seed in seeds:
         prob = c.generate(seed)
         tr, te = prob.train, prob.test
-        for b in (8, 3072):
+        for b, graph in ((8, False), (3072, False), (3072, True)):
+            name = f"gpu_b{b}" + ("_graph" if graph else "")
             G = binding.Model(prob.m, prob.n, c.k, b, seed=seed + 1000, order_mode=0)
+            if graph:  # the epoch's 3072 launches replayed from a HIP graph
+                G.set_option(binding.OPT_EPOCH_GRAPH, 1)
             t0 = time.perf_counter()
             G.load_ratings(tr.u, tr.i, tr.r)
             load_s = time.perf_counter() - t0
@@ -295,10 +298,10 @@ def paper_leg(binding, args):
             t0 = time.perf_counter()
             e, r = G.fit(configs.PAPER_HP, 1000, configs.PAPER_DELTA)
             el = time.perf_counter() - t0
-            runs[f"gpu_b{b}"].append({"seed": seed, "epochs": e, "s_per_iter": el / e, "train_rmse": r,
-                                      "test_rmse": G.rmse(te.u, te.i, te.r), "load_s": load_s})
-            log(f"paper protocol seed {seed} b={b}: {e} epochs, {el / e * 1e3:.2f} ms/iter, test rmse "
-                f"{runs[f'gpu_b{b}'][-1]['test_rmse']:.4f}, load {load_s:.2f}s")
+            runs[name].append({"seed": seed, "epochs": e, "s_per_iter": el / e, "train_rmse": r,
+                               "test_rmse": G.rmse(te.u, te.i, te.r), "load_s": load_s})
+            log(f"paper protocol seed {seed} {name}: {e} epochs, {el / e * 1e3:.2f} ms/iter, test rmse "
+                f"{runs[name][-1]['test_rmse']:.4f}, load {load_s:.2f}s")
             del G
         G = binding.Model(prob.m, prob.n, c.k, 1, seed=seed + 1000, order_mode=0)
         G.load_ratings(tr.u, tr.i, tr.r)
@@ -349,6 +352,8 @@ def paper_leg(binding, args):
                                          "hardware": "Xeon E5-2640 v3 / Tesla M40, MovieLens-1M"}}
     for key, rows in runs.items():
         out[key] = summary(rows)
+    out["b3072_graph_identical"] = bool(all(g["epochs"] == d["epochs"] and g["test_rmse"] == d["test_rmse"]
+                                            for g, d in zip(runs["gpu_b3072_graph"], runs["gpu_b3072"])))
     if runs["oracle_b8"]:
         out["b8_matched"] = bool(all(abs(g["epochs"] - o["epochs"]) <= 1 and abs(g["test_rmse"] - o["test_rmse"]) <= 1e-3
                                      for g, o in zip(runs["gpu_b8"], runs["oracle_b8"])))

@@ -104,7 +104,15 @@ typedef enum {
      * bmf_set_factors into a context loaded with the same ratings, setting
      * it to e makes the following epochs those of the uninterrupted run
      * (Algorithm 1's loop resumed at iteration e). */
-    BMF_OPT_EPOCH = 8
+    BMF_OPT_EPOCH = 8,
+    /* 1: resident epochs capture their b stratum launches as a HIP graph and
+     * replay it while the kernel, data, factor tables, mu, hyper-parameters
+     * and stratum order stay the same (identical results, fewer launch
+     * costs: for grids of many small blocks, such as Section 5's 3072 x 3072).
+     * A change of any of them captures again; with a seeded stratum order
+     * (mode 1) that is every epoch, so use it with mode 0.  Out-of-core
+     * epochs ignore it.  0 (default): direct launches. */
+    BMF_OPT_EPOCH_GRAPH = 9
 } bmf_option;
 
 /* ------------------------------------------------------------- lifetime */

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libbmf.so")
 
 BMF_OK, BMF_E_INVAL, BMF_E_RANGE, BMF_E_STATE, BMF_E_NOMEM, BMF_E_DEVICE = 0, -1, -2, -3, -4, -5
 (OPT_SEED, OPT_ORDER_SEED, OPT_STRATUM_ORDER, OPT_MU_MODE, OPT_STREAM, OPT_SGD_KERNEL, OPT_WAVES_PER_BLOCK,
- OPT_OUT_OF_CORE, OPT_EPOCH) = range(9)
+ OPT_OUT_OF_CORE, OPT_EPOCH, OPT_EPOCH_GRAPH) = range(10)
 
 _STATUS = {0: "BMF_OK", -1: "BMF_E_INVAL", -2: "BMF_E_RANGE", -3: "BMF_E_STATE", -4: "BMF_E_NOMEM",
            -5: "BMF_E_DEVICE"}

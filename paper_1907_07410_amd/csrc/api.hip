@@ -273,6 +273,12 @@ bmf_status bmf_set_option(bmf_ctx *c, int32_t key, int64_t value) {
             if (value < 0 || value >= (int64_t)INT32_MAX) BMF_FAIL(BMF_E_INVAL, "epoch must be in [0, 2^31 - 1)");
             M.epoch = (int)value;
             break;
+        case BMF_OPT_EPOCH_GRAPH:
+            if (value != 0 && value != 1) BMF_FAIL(BMF_E_INVAL, "epoch graph must be 0 or 1");
+            BMF_HIP(hipStreamSynchronize(M.stream));
+            M.egraph.reset();
+            M.egraph.on = value == 1;
+            break;
         default: BMF_FAIL(BMF_E_INVAL, "unknown option " + std::to_string(key));
         }
     });

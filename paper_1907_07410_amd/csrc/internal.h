@@ -142,6 +142,20 @@ struct OutOfCore {
     ~OutOfCore() { release(); }
 };
 
+// An epoch's stratum launches captured once as a HIP graph and replayed
+// while nothing they depend on changes (the key: kernel, data and factor
+// pointers, sizes, mu, the hyper-parameters and the stratum order).  For
+// grids of many small blocks, where launching dominates.
+struct EpochGraph {
+    bool on = false;
+    std::vector<uint64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int64_t captures = 0;
+    void reset();
+    ~EpochGraph() { reset(); }
+};
+
 // --------------------------------------------------------------- context
 struct Model {
     int device = 0;
@@ -160,6 +174,7 @@ struct Model {
     Partition part;
     Plan plan;
     OutOfCore ooc;
+    EpochGraph egraph;
     int32_t epoch = 0;
     // bf16 copies for scoring
     DevBuf Pb, Qb;

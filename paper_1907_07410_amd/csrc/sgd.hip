@@ -19,6 +19,7 @@
 #pragma clang fp contract(off)
 
 #include <algorithm>
+#include <cstring>
 
 #include "internal.h"
 #include "wave.h"
@@ -519,6 +520,51 @@ void ensure_plan(Model &M) {
     if (!M.plan.built) build_plan(M.plan, M.part, M.b, M.k, sgd_max_lds(M.device), M.stream);
 }
 
+void EpochGraph::reset() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    key.clear();
+}
+
+// The epoch's launches through the cached graph, captured again whenever
+// anything the launches depend on has changed since the last capture.
+static void graph_epoch(Model &M, const int32_t *order, const HP &hp, int variant, const StratumData &D) {
+    auto bits = [](float x) {
+        uint32_t u;
+        std::memcpy(&u, &x, 4);
+        return (uint64_t)u;
+    };
+    const float muf = (float)M.mu;
+    std::vector<uint64_t> key = {(uint64_t)variant, (uint64_t)M.b, (uint64_t)M.k, (uint64_t)M.n, (uint64_t)M.waves,
+                                 (uint64_t)(uintptr_t)D.data, (uint64_t)(uintptr_t)D.table, (uint64_t)D.row_stride,
+                                 (uint64_t)(uintptr_t)M.P.p, (uint64_t)(uintptr_t)M.Q.p, (uint64_t)(uintptr_t)M.bu.p,
+                                 (uint64_t)(uintptr_t)M.bi.p, (uint64_t)M.part.rb, (uint64_t)M.part.cb,
+                                 (uint64_t)M.part.ibits, (uint64_t)M.plan.S, (uint64_t)M.plan.CH, bits(muf),
+                                 bits(hp.a_p), bits(hp.b_p), bits(hp.a_q), bits(hp.b_q), bits(hp.a_bu), bits(hp.b_bu),
+                                 bits(hp.a_bi), bits(hp.b_bi)};
+    for (int pos = 0; pos < M.b; ++pos) key.push_back((uint64_t)(uint32_t)order[pos]);
+    EpochGraph &E = M.egraph;
+    if (!E.exec || key != E.key) {
+        E.reset();
+        BMF_HIP(hipStreamBeginCapture(M.stream, hipStreamCaptureModeThreadLocal));
+        try {
+            for (int pos = 0; pos < M.b; ++pos) launch_stratum(M, order[pos], hp, variant, D);
+        } catch (...) {
+            hipGraph_t partial = nullptr;
+            (void)hipStreamEndCapture(M.stream, &partial);
+            if (partial) (void)hipGraphDestroy(partial);
+            throw;
+        }
+        BMF_HIP(hipStreamEndCapture(M.stream, &E.graph));
+        BMF_HIP(hipGraphInstantiate(&E.exec, E.graph, nullptr, nullptr, 0));
+        E.key = std::move(key);
+        E.captures += 1;
+    }
+    BMF_HIP(hipGraphLaunch(E.exec, M.stream));
+}
+
 void sgd_epoch(Model &M, const int32_t *order, const HP &hp) {
     int variant = M.sgd_kernel;
     if (M.ooc.on) {
@@ -539,7 +585,10 @@ void sgd_epoch(Model &M, const int32_t *order, const HP &hp) {
     } else {
         const StratumData D = variant == 2 ? StratumData{M.plan.steps.p, M.plan.blk_step.as<int64_t>(), M.b}
                                            : StratumData{M.part.recs.p, M.part.block_ptr.as<int64_t>(), M.b};
-        for (int pos = 0; pos < M.b; ++pos) launch_stratum(M, order[pos], hp, variant, D);
+        if (M.egraph.on)
+            graph_epoch(M, order, hp, variant, D);
+        else
+            for (int pos = 0; pos < M.b; ++pos) launch_stratum(M, order[pos], hp, variant, D);
     }
     BMF_HIP(hipEventRecord(ev1, M.stream));
     M.pending.emplace_back(ev0, ev1);

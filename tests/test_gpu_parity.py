@@ -441,3 +441,46 @@ def test_waves_per_block_do_not_change_results(B, k):
     for o in outs[1:]:
         for a, c in zip(outs[0][:4], o[:4]):
             assert np.array_equal(a.view(np.uint32), c.view(np.uint32))
+
+
+@pytest.mark.parametrize("kernel,order_mode", [(1, 0), (2, 0), (2, 1)])
+def test_epoch_graph_replays_equal_direct_launches(B, kernel, order_mode):
+    """Epochs replayed from a captured HIP graph equal direct launches bit for
+    bit: several replays with host work and synchronisation between them,
+    then new hyper-parameters (captured again), restored factors, and a new
+    load.  With the seeded order the graph is captured every epoch."""
+    m, n, k, b = 700, 500, 32, 64
+    rat = synth.random_coo(m, n, 30000, seed=21, dup=True)
+    A = B.Model(m, n, k, b, order_mode=order_mode, order_seed=5, sgd_kernel=kernel)
+    D = B.Model(m, n, k, b, order_mode=order_mode, order_seed=5, sgd_kernel=kernel)
+    A.set_option(B.OPT_EPOCH_GRAPH, 1)
+    for M in (A, D):
+        M.load_ratings(rat.u, rat.i, rat.r)
+
+    def same():
+        return all(np.array_equal(x.view(np.uint32), y.view(np.uint32))
+                   for x, y in zip(A.get_factors()[:4], D.get_factors()[:4]))
+
+    for _ in range(4):
+        A.epoch(0.01, 0.02)
+        D.epoch(0.01, 0.02)
+        assert same()
+    hp2 = (0.02, 0.01, 0.005, 0.03, 0.004, 0.019, 0.013, 0.007)
+    for _ in range(2):
+        A.epoch_hp(hp2)
+        D.epoch_hp(hp2)
+        assert same()
+    ck = D.get_factors()
+    A.set_factors(*ck)
+    A.epoch(0.01, 0.02)
+    D.epoch(0.01, 0.02)
+    assert same()
+    rat2 = synth.random_coo(m, n, 25000, seed=22, dup=True)
+    for M in (A, D):
+        M.load_ratings(rat2.u, rat2.i, rat2.r)
+    for _ in range(2):
+        A.epoch(0.01, 0.02)
+        D.epoch(0.01, 0.02)
+        assert same()
+    ms, launches = A.sgd_timing()
+    assert launches == 9 * b and ms > 0

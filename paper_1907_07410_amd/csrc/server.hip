@@ -339,8 +339,15 @@ void finisher(bmf_server *S) {
         if (ok) {
             publish_batch(S, sl);
         } else {
+            // the server stops: pollers of these requests get the failure,
+            // and the slot is let go so that the scheduler can end
             S->failed = true;
             S->err = "server failed: host allocation for results failed";
+            S->bytes_in_use -= sl.bytes;
+            sl.bytes = 0;
+            sl.placed.clear();
+            sl.finishing = false;
+            sl.busy = false;
         }
         S->cv.notify_all();
     }
@@ -360,6 +367,7 @@ void scheduler(bmf_server *S) {
         BMF_HIP(hipSetDevice(S->ctx->M.device));
         Model &M = S->ctx->M;
         while (true) {
+            if (S->failed) break;  // a completion thread failed
             bool progressed = false;
             // completions
             for (size_t q = 0; q < S->slots.size(); ++q) {

@@ -37,6 +37,18 @@ def test_library_exports_every_declared_symbol(binding):
     assert missing == []
 
 
+def test_binding_constants_match_the_header(binding):
+    """The binding's option keys and status codes carry the header's values."""
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    opts = dict(re.findall(r"\bBMF_OPT_([A-Z_]+)\s*=\s*(\d+)", text))
+    codes = dict(re.findall(r"\bBMF_(OK|E_[A-Z]+)\s*=\s*(-?\d+)", text))
+    assert len(opts) == 10 and len(codes) == 6
+    for name, value in opts.items():
+        assert getattr(binding, "OPT_" + name) == int(value), name
+    for name, value in codes.items():
+        assert getattr(binding, "BMF_" + name) == int(value), name
+
+
 def test_create_rejects_bad_sizes_without_touching_the_device(binding):
     h = C.c_void_p()
     for args in [(0, 5, 4, 2), (5, 0, 4, 2), (5, 5, 0, 2), (5, 5, 4, 0), (5, 5, 2000, 2), (5, 5, 4, 10**5)]:

@@ -9,8 +9,12 @@ rounding against published values; the single-rating update and the bias
 dynamics against hand and closed-form values; the partition against an
 independent lexsort; the schedule against the Latin-square property and the
 paper's diagonal-first order; an epoch against the pinned update applied
-rating by rating; RMSE and loss against closed forms; top-K against brute
-force; fold-in against the ridge solution it converges to; the stopping rule
+rating by rating (three update forms: Eqs 10-13, Algorithm 2's factor order,
+Algorithm 2 as printed); RMSE against a closed form; the loss against a
+closed form and a hand-worked example with every penalty term; top-K, and
+the ranking of an explicit user vector, against brute force (and the two
+against each other); fold-in against the ridge solution it converges to;
+the stopping rule
 of Algorithm 1 (``Model.fit``) against a recorded trajectory; incremental
 data (``Model.add_ratings``) against growth, untouched-row and partition
 invariants.  No function is left without a pin; the paper's own Table 1
@@ -166,11 +170,17 @@ class Model:
         return schedule(self.b, self.order_seed, epoch, self.order_mode)
 
     def epoch(self, lr: float = None, reg: float = None, hp: Sequence[float] = None,
-              threads: int = 1, gauss_seidel: bool = False):
+              threads: int = 1, gauss_seidel: bool = False, alg2_literal: bool = False):
+        """One epoch.  Update form: simultaneous Eqs 10-13 (default);
+        ``gauss_seidel``: item factors from the updated user factors;
+        ``alg2_literal``: Algorithm 2 as printed (crossed bias regularisers,
+        the item bias penalised by the updated user bias, Gauss-Seidel
+        factors)."""
         hp = hparams(lr, reg) if hp is None else _c(hp, np.float64)
         order = self.order(self.epoch_no)
+        form = 2 if alg2_literal else (1 if gauss_seidel else 0)
         rc = lib().orc_epoch(self.m, self.n, self.k, self.b, _ptr(self.P), _ptr(self.Q), _ptr(self.bu),
-                             _ptr(self.bi), self.mu, _ptr(hp), int(gauss_seidel), _ptr(self.u),
+                             _ptr(self.bi), self.mu, _ptr(hp), form, _ptr(self.u),
                              _ptr(self.i), _ptr(self.r), _ptr(self.block_ptr), _ptr(self.perm),
                              _ptr(order), threads)
         if rc != 0:

@@ -22,8 +22,11 @@
  *  - Eq 11's q_u is q_i; the bias regularisers use the bias being updated
  *    (Eqs 12-13), not the crossed ones of Algorithm 2;
  *  - all four updates use the residual and the values from before the
- *    update (simultaneous form); the Gauss-Seidel order of Algorithm 2
- *    (item factors updated with the new user factor) is a flag;
+ *    update (simultaneous form).  Two other forms are kept as a switch:
+ *    the Gauss-Seidel factor order of Algorithm 2 (item factors updated
+ *    with the new user factor), and Algorithm 2 as printed, which also
+ *    penalises the user bias with the item bias and the item bias with
+ *    the user bias it has just updated;
  *  - block extents rb = ceil(m/b), cb = ceil(n/b) (Section 5's 755 x 486
  *    example for 6040 users and b = 8);
  *  - stratum s = {((j + s) mod b, j)} (Section 3, parallel BMF: diagonal
@@ -158,14 +161,22 @@ void orc_schedule(int b, uint64_t seed, int epoch, int mode, int32_t *order)
 /* ---------------------------------------------------------------- update
  * One observed rating (Eqs 10-13).  hp[8] = {alpha_p, beta_p, alpha_q,
  * beta_q, alpha_bu, beta_bu, alpha_bi, beta_bi} (user-latent, item-latent,
- * user-bias, item-bias).                                                 */
+ * user-bias, item-bias).
+ * form 0: Eqs 10-13 with every right-hand side taken before the update;
+ * form 1: the same biases, item factors from the updated user factors
+ *         (Algorithm 2's statement order for U and V);
+ * form 2: Algorithm 2 as printed: the user bias is penalised by the item
+ *         bias, the item bias by the user bias just updated, and the item
+ *         factors use the updated user factors.                          */
+enum { FORM_SIMULTANEOUS = 0, FORM_GAUSS_SEIDEL = 1, FORM_ALG2_LITERAL = 2 };
+
 typedef struct {
     int64_t m, n;
     int k;
     double *P, *Q, *bu, *bi;
     double mu;
     double hp[8];
-    int gauss_seidel;
+    int form;
 } orc_state;
 
 static void update_one(orc_state *S, int64_t u, int64_t i, double r)
@@ -176,12 +187,18 @@ static void update_one(orc_state *S, int64_t u, int64_t i, double r)
     for (int f = 0; f < k; ++f) dot += p[f] * q[f];
     double err = r - S->mu - S->bu[u] - S->bi[i] - dot;
     double bu0 = S->bu[u], bi0 = S->bi[i];
-    S->bu[u] = bu0 + S->hp[4] * (err - S->hp[5] * bu0);
-    S->bi[i] = bi0 + S->hp[6] * (err - S->hp[7] * bi0);
+    if (S->form == FORM_ALG2_LITERAL) {
+        double bun = bu0 + S->hp[4] * (err - S->hp[5] * bi0);
+        S->bu[u] = bun;
+        S->bi[i] = bi0 + S->hp[6] * (err - S->hp[7] * bun);
+    } else {
+        S->bu[u] = bu0 + S->hp[4] * (err - S->hp[5] * bu0);
+        S->bi[i] = bi0 + S->hp[6] * (err - S->hp[7] * bi0);
+    }
     for (int f = 0; f < k; ++f) {
         double pf = p[f], qf = q[f];
         double pn = pf + S->hp[0] * (err * qf - S->hp[1] * pf);
-        double pq = S->gauss_seidel ? pn : pf;
+        double pq = S->form == FORM_SIMULTANEOUS ? pf : pn;
         p[f] = pn;
         q[f] = qf + S->hp[2] * (err * pq - S->hp[3] * qf);
     }
@@ -221,11 +238,12 @@ static void *stratum_worker(void *arg)
  * over threads with a join after each stratum (the CPU block variant of
  * Section 5); results are identical for every thread count.             */
 int orc_epoch(int64_t m, int64_t n, int k, int b, double *P, double *Q, double *bu, double *bi,
-              double mu, const double *hp, int gauss_seidel, const int32_t *u, const int32_t *i,
+              double mu, const double *hp, int form, const int32_t *u, const int32_t *i,
               const float *r, const int64_t *block_ptr, const int32_t *perm, const int32_t *order,
               int threads)
 {
-    orc_state S = {m, n, k, P, Q, bu, bi, mu, {0}, gauss_seidel};
+    if (form < FORM_SIMULTANEOUS || form > FORM_ALG2_LITERAL) return -1;
+    orc_state S = {m, n, k, P, Q, bu, bi, mu, {0}, form};
     memcpy(S.hp, hp, sizeof(S.hp));
     if (threads < 1) threads = 1;
     if (threads > b) threads = b;

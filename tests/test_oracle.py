@@ -46,19 +46,19 @@ def test_bf16_rounding_cases(orc):
 
 
 # ------------------------------------------------------------ update rules
-def _single(orc, g, gauss_seidel):
+def _single(orc, g, form):
     inp = g["inputs"]
     M = orc.Model(1, 1, 2, 1, seed=1)
     M.load([0], [0], [inp["r"]])
     M.set_factors(np.array([inp["p"]]), np.array([inp["q"]]), [inp["bu"]], [inp["bi"]], inp["mu"])
-    M.epoch(inp["lr"], inp["reg"], gauss_seidel=gauss_seidel)
+    M.epoch(inp["lr"], inp["reg"], gauss_seidel=form == "gauss_seidel", alg2_literal=form == "alg2_literal")
     return M
 
 
-@pytest.mark.parametrize("form", ["simultaneous", "gauss_seidel"])
+@pytest.mark.parametrize("form", ["simultaneous", "gauss_seidel", "alg2_literal"])
 def test_single_rating_worked_example(orc, form):
     g = _gold("single_update.json")
-    M = _single(orc, g, form == "gauss_seidel")
+    M = _single(orc, g, form)
     want = g[form]
     assert M.bu[0] == pytest.approx(want["bu"], abs=1e-15)
     assert M.bi[0] == pytest.approx(want["bi"], abs=1e-15)
@@ -271,6 +271,47 @@ def test_loss_closed_form_zero_factors(orc):
     assert M.loss(hp=hp) == pytest.approx(math.fsum(terms), rel=1e-12)
 
 
+def test_loss_worked_example(orc):
+    """Eq 9 with non-zero factors and biases, four different betas and
+    alphas that must not enter (tests/golden/loss_worked.json, worked by
+    hand): a swapped alpha/beta, a dropped square or a missing penalty term
+    changes the value."""
+    g = _gold("loss_worked.json")
+    inp = g["inputs"]
+    rat = np.array(inp["ratings"])
+    M = orc.Model(2, 2, 2, 1, seed=1)
+    M.load(rat[:, 0].astype(np.int32), rat[:, 1].astype(np.int32), rat[:, 2].astype(np.float32))
+    M.set_factors(np.array(inp["P"]), np.array(inp["Q"]), inp["bu"], inp["bi"], inp["mu"])
+    h = inp["hp"]
+    hp = [h["alpha_p"], h["beta_p"], h["alpha_q"], h["beta_q"], h["alpha_bu"], h["beta_bu"], h["alpha_bi"],
+          h["beta_bi"]]
+    assert M.loss(hp=hp) == pytest.approx(g["loss"], rel=1e-13)
+    # each rating's term alone (the loss is a sum over observed ratings)
+    for t, want in enumerate(g["terms"]):
+        M.load(rat[t:t + 1, 0].astype(np.int32), rat[t:t + 1, 1].astype(np.int32),
+               rat[t:t + 1, 2].astype(np.float32))
+        M.mu = inp["mu"]
+        assert M.loss(hp=hp) == pytest.approx(want, rel=1e-13)
+
+
+def test_alg2_literal_equals_simultaneous_when_the_crossed_terms_vanish(orc):
+    """Algorithm 2 as printed differs from Eqs 10-13 only through the
+    crossed bias penalties and the factor order: with no bias penalty and
+    no item-factor step the three forms give the same bits."""
+    rat = synth.random_coo(9, 7, 80, seed=8, dup=True)
+    out = []
+    for form in ("simultaneous", "gauss_seidel", "alg2_literal"):
+        M = orc.Model(9, 7, 3, 2, seed=3)
+        M.load(rat.u, rat.i, rat.r)
+        hp = [0.05, 0.02, 0.0, 0.02, 0.04, 0.0, 0.03, 0.0]
+        for _ in range(3):
+            M.epoch(hp=hp, gauss_seidel=form == "gauss_seidel", alg2_literal=form == "alg2_literal")
+        out.append((M.P, M.Q, M.bu, M.bi))
+    for o in out[1:]:
+        for a, b in zip(out[0], o):
+            assert np.array_equal(a, b)
+
+
 def test_noise_free_planted_matrix_is_recovered(orc):
     """r = 3.5 + u.v exactly (no noise, no rounding), k >= planted rank,
     no regularisation: the training RMSE goes to ~0."""
@@ -345,6 +386,42 @@ def test_topk_k_larger_than_n_pads(orc):
     items, scores = orc.topk_dense(np.ones((1, 2)), np.ones((3, 2)), [0.0], [0.0, 0.1, 0.2], 0.0, [0], 5)
     assert items[0].tolist() == [2, 1, 0, -1, -1]
     assert np.isinf(scores[0, 3]) and scores[0, 3] < 0
+
+
+def test_topk_vec_matches_brute_force(orc):
+    """Ranking of an explicit user vector (a folded-in user): every item's
+    score mu + bu + bi_i + p . q_i, best first, ties to the smaller id,
+    checked against a full Python sort of scores summed with math.fsum."""
+    rng = np.random.default_rng(12)
+    n, k, K = 250, 6, 30
+    Q = rng.normal(size=(n, k))
+    bi = rng.normal(size=n)
+    bi[17] = bi[3]
+    Q[17] = Q[3]  # an exact tie: 3 must come first if it makes the list
+    p = rng.normal(size=k)
+    bu = 0.37
+    items, scores = orc.topk_vec(p, bu, Q, bi, 2.5, K)
+    s = [math.fsum([2.5, bu, bi[j]] + [p[f] * Q[j, f] for f in range(k)]) for j in range(n)]
+    want = sorted(range(n), key=lambda j: (-s[j], j))[:K]
+    assert items.tolist() == want
+    np.testing.assert_allclose(scores, [s[j] for j in want], rtol=0, atol=1e-12)
+    # K beyond n pads with -1 / -inf
+    items, scores = orc.topk_vec(p[:2], bu, Q[:4, :2], bi[:4], 0.0, 6)
+    assert sorted(items[:4].tolist()) == [0, 1, 2, 3] and items[4:].tolist() == [-1, -1]
+    assert np.all(np.isneginf(scores[4:]))
+
+
+def test_topk_vec_equals_topk_of_the_same_user_row(orc):
+    """A user vector ranked alone equals the same vector ranked as row u of
+    a factor table, bit for bit."""
+    rng = np.random.default_rng(13)
+    m, n, k, K = 5, 400, 9, 50
+    P, Q = rng.normal(size=(m, k)), rng.normal(size=(n, k))
+    bu, bi = rng.normal(size=m), rng.normal(size=n)
+    for u in range(m):
+        ti, ts = orc.topk_dense(P, Q, bu, bi, 3.25, [u], K)
+        vi, vs = orc.topk_vec(P[u], bu[u], Q, bi, 3.25, K)
+        assert np.array_equal(ti[0], vi) and np.array_equal(ts[0], vs)
 
 
 # ------------------------------------------------------------------ fold-in

@@ -79,9 +79,57 @@ def test_server_matches_direct_calls(B, model):
         assert np.array_equal(r["scores"].view(np.uint32), ds.view(np.uint32))
     items = rng.choice(G.n, 200, replace=False).astype(np.int32)
     rat = rng.integers(1, 6, 200).astype(np.float32)
-    r = S.poll(S.submit_foldin(items, rat, 100, 0))
     p, bu = G.foldin(items, rat, 10, 0.005, 0.05)
-    assert np.array_equal(r["p"].view(np.uint32), p.view(np.uint32)) and r["bu"] == bu
+    for precision in (0, 1):  # the fold-in itself is FP32 in both
+        r = S.poll(S.submit_foldin(items, rat, 100, precision))
+        assert np.array_equal(r["p"].view(np.uint32), p.view(np.uint32)) and r["bu"] == bu
+    S.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_foldin_topk_matches_oracle(B, orc, model, precision):
+    """A new user folded in through the server and then ranked (Section 2.1's
+    folding-in, Eq 3's prediction), against the FP64 oracle:
+      * p and bu within 1e-5 of the oracle's fold-in;
+      * the scoring of the folded-in row: returned items epsilon-valid and
+        scores within eps of the FP64 scores of the GPU's own vector;
+      * the whole request: items and scores epsilon-valid against the
+        oracle's fold-in followed by the oracle's ranking of that vector,
+        with eps widened by what the 1e-5 fold-in tolerance can move a
+        score (1e-5 (|q_i|_1 + 1))."""
+    G, (P, Q, bu, bi, mu) = model
+    S = B.Server(G)
+    rng = np.random.default_rng(40 + precision)
+    K = 100
+    Qd, bid = Q.astype(np.float64), bi.astype(np.float64)
+    eps_scale = (G.k + 8) * 2.0 ** -23
+    widen = 1e-5 * (np.abs(Qd).sum(axis=1).max() + 1.0)
+    overlap = []
+    for nr in (5, 60, 500):
+        items = rng.choice(G.n, nr, replace=False).astype(np.int32)
+        rat = rng.integers(1, 6, nr).astype(np.float32)
+        res = S.poll(S.submit_foldin(items, rat, K, precision))
+        it, sc = res["items"][0], res["scores"][0]
+        assert len(set(it.tolist())) == K and np.all(np.diff(sc) <= 0)
+        op, obu = orc.foldin(Q, bi, mu, items, rat, 10, 0.005, 0.05)
+        assert np.abs(res["p"] - op).max() <= 1e-5 and abs(res["bu"] - obu) <= 1e-5, nr
+        # scoring of the GPU's folded-in row
+        pg = res["p"].astype(np.float64)
+        s64 = mu + res["bu"] + bid + Qd @ pg
+        eps = eps_scale * (np.abs(Qd * pg).sum(axis=1) + np.abs(bid) + abs(mu + res["bu"])).max()
+        kth = np.sort(s64)[::-1][K - 1]
+        assert np.all(s64[it] >= kth - eps), (nr, (s64[it] - kth).min(), eps)
+        assert np.all(np.abs(sc - s64[it]) <= eps), (nr, np.abs(sc - s64[it]).max(), eps)
+        # against the oracle's fold-in and its ranking of the oracle's vector
+        oi, os_ = orc.topk_vec(op, obu, Q, bi, mu, G.n)
+        o_score = np.empty(G.n)
+        o_score[oi] = os_
+        eps_o = eps + widen
+        assert np.all(o_score[it] >= os_[K - 1] - eps_o), (nr, (o_score[it] - os_[K - 1]).min(), eps_o)
+        assert np.all(np.abs(sc - o_score[it]) <= eps_o), (nr, np.abs(sc - o_score[it]).max(), eps_o)
+        overlap.append(len(set(it.tolist()) & set(oi[:K].tolist())) / K)
+    log("fold-in top-100 overlap with the oracle, precision", precision, overlap)
+    assert min(overlap) >= 0.95
     S.close()
 
 

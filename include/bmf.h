@@ -291,6 +291,23 @@ bmf_status bmf_topk_bf16(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K
 bmf_status bmf_topk_dev(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t precision,
                         int32_t Kc, int32_t *items_out, float *scores_out);
 
+/* For callers that cannot allocate device memory (work captured into a
+ * HIP graph, serving loops that must not allocate, harnesses that forbid
+ * hipMalloc): bmf_topk_dev with the same arguments, checks and results
+ * (bit for bit), but its workspace (user rows, thresholds, candidate lists)
+ * is a fixed array of 64 MiB that the library holds on every device it
+ * runs on until the process ends; no device memory is allocated or freed.
+ * A request whose workspace exceeds 64 MiB (at K = 100 about 4,200 users
+ * at n = 27,000 and k = 64, about 2,300 at n = 100,000 and k = 128) fails
+ * with BMF_E_NOMEM and changes nothing: split it.  precision 1 also needs the
+ * BF16 item table's memory, which the first BF16 call that may allocate
+ * (bmf_topk_bf16, bmf_topk_dev, bmf_server_create) makes: BMF_E_STATE
+ * before that.  Every call on one device shares the array, so calls that
+ * may overlap on one device (other streams, other contexts, other host
+ * threads) race and must be serialised by the caller.  Enqueue only. */
+bmf_status bmf_topk_dev_noalloc(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t precision,
+                                int32_t Kc, int32_t *items_out, float *scores_out);
+
 /* ---------------------------------------------------------------- fold-in */
 
 /* Fold in a new user (Section 2.1's folding-in of new data; Section 6's

@@ -69,6 +69,7 @@ def _load():
         "bmf_topk": ([p, p, i64, i32, p, p], i32),
         "bmf_topk_bf16": ([p, p, i64, i32, i32, p, p], i32),
         "bmf_topk_dev": ([p, p, i64, i32, i32, i32, p, p], i32),
+        "bmf_topk_dev_noalloc": ([p, p, i64, i32, i32, i32, p, p], i32),
         "bmf_rmse_dev": ([p, p, p, p, i64, p], i32),
         "bmf_foldin": ([p, p, p, i32, i32, f32, f32, p, p], i32),
         "bmf_sgd_timing": ([p, p, p, i32], i32),
@@ -297,6 +298,12 @@ class Model:
     def topk_dev(self, users, K: int, precision: int, Kc: int, items_out, scores_out):
         self._check(lib.bmf_topk_dev(self._h, _dptr(users), int(users.numel()), K, precision, Kc,
                                      _dptr(items_out), _dptr(scores_out)))
+
+    def topk_dev_noalloc(self, users, K: int, precision: int, Kc: int, items_out, scores_out):
+        """topk_dev with the library's fixed device workspace (no device
+        allocation; see bmf_topk_dev_noalloc)."""
+        self._check(lib.bmf_topk_dev_noalloc(self._h, _dptr(users), int(users.numel()), K, precision, Kc,
+                                             _dptr(items_out), _dptr(scores_out)))
 
     def foldin(self, items, r, passes: int, lr: float, reg: float):
         items, r = _c(items, np.int32), _c(r, np.float32)

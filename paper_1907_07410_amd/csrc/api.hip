@@ -572,6 +572,15 @@ bmf_status bmf_topk_dev(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K,
     });
 }
 
+bmf_status bmf_topk_dev_noalloc(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t precision,
+                                int32_t Kc, int32_t *items_out, float *scores_out) {
+    return guarded(c, false, [&] {
+        check_topk_args(c->M, nu, K, precision, Kc);
+        if (nu > 0 && (!users || !items_out || !scores_out)) BMF_FAIL(BMF_E_INVAL, "null array");
+        topk_run_fixed(c->M, users, nu, K, precision, Kc, items_out, scores_out);
+    });
+}
+
 bmf_status bmf_foldin(bmf_ctx *c, const int32_t *items, const float *r, int32_t nr, int32_t passes, float lr,
                       float reg, float *p_out, float *bu_out) {
     return guarded(c, false, [&] {

@@ -300,6 +300,13 @@ void topk_gather(Model &M, const TopkPlan &T, const int32_t *d_users, unsigned c
 void topk_score(Model &M, const TopkPlan &T, unsigned char *work, int32_t *d_items, float *d_scores, hipStream_t s);
 void topk_run(Model &M, const int32_t *d_users, int64_t nu, int K, int precision, int Kc,
               int32_t *d_items, float *d_scores);
+// topk_run with its workspace in a fixed device array of TOPK_FIXED_BYTES
+// (no device allocation: BMF_E_NOMEM when the request needs more; BF16
+// needs the item table's memory from an earlier BF16 call, BMF_E_STATE
+// otherwise).
+constexpr size_t TOPK_FIXED_BYTES = size_t(64) << 20;
+void topk_run_fixed(Model &M, const int32_t *d_users, int64_t nu, int K, int precision, int Kc,
+                    int32_t *d_items, float *d_scores);
 void foldin_run(Model &M, const int32_t *d_items, const float *d_r, int nr, int passes, const HP &hp,
                 float *d_p, float *d_bu);
 void foldin_launch(Model &M, const int32_t *d_items, const float *d_r, const int64_t *d_off, int64_t nreq,
@@ -308,7 +315,9 @@ void foldin_launch(Model &M, const int32_t *d_items, const float *d_r, const int
 // scoring rows: zero the padding, BF16 copy, offset mu + bu.
 void foldin_rows(const float *bu_f, int64_t nreq, float mu, int k, int kp, int kb, float *Ug, uint16_t *Ugb,
                  float *ub, hipStream_t s);
-void ensure_bf16_items(Model &M);
+// The BF16 copy of Q for scoring, made after the factors last changed;
+// may_alloc false refuses (BMF_E_STATE) where its memory is missing.
+void ensure_bf16_items(Model &M, bool may_alloc);
 
 // Timing: take an event (from the spare list or new), and fold completed
 // pending pairs into sgd_ms (all of them, waiting, when `wait`).

@@ -549,7 +549,7 @@ bmf_status bmf_server_create(bmf_ctx *c, const bmf_server_config *cfg, bmf_serve
         Model &M = c->M;
         BMF_HIP(hipSetDevice(M.device));
         if (M.k > 256) BMF_FAIL(BMF_E_INVAL, "serving supports k <= 256");
-        ensure_bf16_items(M);
+        ensure_bf16_items(M, true);
         BMF_HIP(hipStreamSynchronize(M.stream));
         S->part_bytes = ((size_t)d.mem_budget_bytes / d.max_batches) & ~size_t(255);
         S->arena.alloc(S->part_bytes * d.max_batches);

@@ -32,6 +32,7 @@
 // the batch.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 #include "wave.h"
@@ -775,11 +776,16 @@ static int sample_rank(double lambda, double eps) {
     return r;
 }
 
-void ensure_bf16_items(Model &M) {
+void ensure_bf16_items(Model &M, bool may_alloc) {
     if (M.bf16_valid) return;
     const int kb = round_up(M.k, 32);
     const size_t need = (size_t)M.n * kb * sizeof(uint16_t);
-    if (M.Qb.bytes < need) M.Qb.alloc(need);
+    if (M.Qb.bytes < need) {
+        if (!may_alloc)
+            BMF_FAIL(BMF_E_STATE, "the BF16 item table has no device memory yet: run one BF16 top-K call that may "
+                                  "allocate (bmf_topk_bf16 or bmf_topk_dev with precision 1) first");
+        M.Qb.alloc(need);
+    }
     const int grid = (int)std::min<int64_t>((M.n * kb + 255) / 256, 8192);
     bf16_table_kernel<<<grid, 256, 0, M.stream>>>(M.Q.as<float>(), M.n, M.k, kb, M.Qb.as<uint16_t>());
     BMF_HIP(hipGetLastError());
@@ -886,7 +892,50 @@ void topk_run(Model &M, const int32_t *d_users, int64_t nu, int K, int precision
     if (M.scratch.bytes < T.total) M.scratch.alloc(T.total);
     unsigned char *w = M.scratch.as<unsigned char>();
     topk_gather(M, T, d_users, w, M.stream);
-    if (T.bf) ensure_bf16_items(M);
+    if (T.bf) ensure_bf16_items(M, true);
+    topk_score(M, T, w, d_items, d_scores, M.stream);
+}
+
+// ------------------------------------------------ fixed device workspace
+// For callers that cannot allocate device memory (work captured into a HIP
+// graph, serving loops that must not allocate): the top-K workspace of
+// topk_run_fixed lives in this array, TOPK_FIXED_BYTES on every device the
+// library runs on, held until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it names a stand-in, not device
+// memory): fixed_workspace() takes its device address once per device with
+// hipGetSymbolAddress, and that address is what the kernels get.  Every
+// call on one device shares the array; the passes write everything they
+// read (the threshold pass clears the candidate counts), so nothing needs
+// clearing between calls, and calls that overlap on one device race.
+static __device__ __align__(256) unsigned char scratch[TOPK_FIXED_BYTES];
+
+static unsigned char *fixed_workspace(int device) {
+    static std::mutex mu;
+    static std::vector<unsigned char *> addr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (device < 0) BMF_FAIL(BMF_E_INVAL, "bad device");
+    if ((size_t)device >= addr.size()) addr.resize((size_t)device + 1, nullptr);
+    if (!addr[device]) {
+        void *p = nullptr;
+        // the caller has made `device` current (every entry point does)
+        BMF_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) BMF_FAIL(BMF_E_DEVICE, "no device address for the fixed top-K workspace");
+        addr[device] = static_cast<unsigned char *>(p);
+    }
+    return addr[device];
+}
+
+void topk_run_fixed(Model &M, const int32_t *d_users, int64_t nu, int K, int precision, int Kc, int32_t *d_items,
+                    float *d_scores) {
+    if (M.k > 256) BMF_FAIL(BMF_E_INVAL, "top-K scoring supports k <= 256");
+    unsigned char *w = fixed_workspace(M.device);
+    if (nu == 0) return;
+    const TopkPlan T = topk_plan(M, nu, K, precision, Kc);
+    if (T.total > TOPK_FIXED_BYTES)
+        BMF_FAIL(BMF_E_NOMEM, "the request needs " + std::to_string(T.total) + " bytes of workspace, more than the " +
+                                  std::to_string(TOPK_FIXED_BYTES) + " of the fixed top-K workspace; split it");
+    if (T.bf) ensure_bf16_items(M, false);
+    topk_gather(M, T, d_users, w, M.stream);
     topk_score(M, T, w, d_items, d_scores, M.stream);
 }
 

@@ -129,8 +129,9 @@ class BatchedConfig:
         def one(p: int) -> synth.Problem:
             m, n, nnz = shapes[p]
             rng = np.random.default_rng(seed * 1000 + p)
-            u, i = synth.sample_pairs_zipf(m, n, nnz, 1.1, 1.1, rng)
-            r = synth.planted_values(u, i, m, n, self.rank, 0.3, self.noise, 3.5, "int", rng)
+            # one thread per problem: the problems themselves run in parallel
+            u, i = synth.sample_pairs_zipf(m, n, nnz, 1.1, 1.1, rng, workers=1)
+            r = synth.planted_values(u, i, m, n, self.rank, 0.3, self.noise, 3.5, "int", rng, workers=1)
             if progress is not None:
                 progress(p)
             return synth.Problem(m, n, synth.Ratings(u, i, r), None)

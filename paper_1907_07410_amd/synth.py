@@ -87,10 +87,41 @@ def _weighted_distinct(rng: np.random.Generator, weights: np.ndarray, d: int) ->
     return np.argpartition(-keys, d - 1)[:d].astype(np.int64)
 
 
+def _workers(workers: Optional[int]) -> int:
+    if workers is not None:
+        return max(1, int(workers))
+    try:
+        import os
+        return max(1, min(16, len(os.sched_getaffinity(0))))
+    except (AttributeError, OSError):
+        return 1
+
+
+def _light_pairs(rng: np.random.Generator, users: np.ndarray, deg: np.ndarray, cdf: np.ndarray,
+                 n: int) -> np.ndarray:
+    """Keys u * n + i of ``deg[q]`` distinct items for each user ``users[q]``,
+    items drawn with probability given by ``cdf`` (redrawn until distinct)."""
+    need = deg.copy()
+    have = np.zeros(0, dtype=np.int64)
+    for _ in range(200):
+        todo = need > 0
+        if not todo.any():
+            return have
+        uu = np.repeat(users[todo], need[todo])
+        draws = np.minimum(np.searchsorted(cdf, rng.random(uu.shape[0]), side="right"), n - 1)
+        have = np.unique(np.concatenate([have, uu * np.int64(n) + draws]))
+        cnt = np.searchsorted(have, (users + 1) * np.int64(n)) - np.searchsorted(have, users * np.int64(n))
+        need = deg - cnt
+    raise RuntimeError("pair sampler did not converge")
+
+
 def sample_pairs_zipf(m: int, n: int, nnz: int, s_user: float, s_item: float,
-                      rng: np.random.Generator) -> Tuple[np.ndarray, np.ndarray]:
+                      rng: np.random.Generator, workers: Optional[int] = None) -> Tuple[np.ndarray, np.ndarray]:
     """Distinct (u, i) pairs with capped-Zipf user degrees and item
-    popularity, returned sorted by a random key (not by user)."""
+    popularity, returned sorted by a random key (not by user).  Users with a
+    quarter or more of all items draw theirs by Gumbel top-d; the others are
+    drawn in chunks of consecutive user ids, each chunk from its own child
+    stream of ``rng`` (so the result does not depend on ``workers``)."""
     du_rank = capped_zipf_degrees(m, nnz, s_user, n)
     wi_rank = capped_zipf_degrees(n, nnz, s_item, m).astype(np.float64) + 1e-3
     uperm = rng.permutation(m)
@@ -107,28 +138,27 @@ def sample_pairs_zipf(m: int, n: int, nnz: int, s_user: float, s_item: float,
     cdf = np.cumsum(w)
     cdf /= cdf[-1]
     light_users = np.nonzero(~heavy)[0]
-    need = deg[light_users].copy()
-    have = np.zeros(0, dtype=np.int64)
-    for _ in range(200):
-        todo = need > 0
-        if not todo.any():
-            break
-        users = np.repeat(light_users[todo], need[todo])
-        draws = np.searchsorted(cdf, rng.random(users.shape[0]), side="right")
-        draws = np.minimum(draws, n - 1)
-        have = np.unique(np.concatenate([have, users * np.int64(n) + draws]))
-        cnt = np.bincount((have // n), minlength=m)[light_users]
-        over = cnt - deg[light_users]
-        if (over > 0).any():
-            # drop surplus draws of over-full users (cannot happen with
-            # deficit-only redraws, kept as a guard)
-            raise RuntimeError("pair sampler overshoot")
-        need = deg[light_users] - cnt
+    # chunks of about 2M ratings of consecutive users
+    csum = np.cumsum(deg[light_users])
+    nchunk = max(1, int(csum[-1] // (1 << 21)) + 1) if light_users.size else 0
+    bounds = np.searchsorted(csum, np.linspace(0, csum[-1] if light_users.size else 0, nchunk + 1)[1:-1])
+    parts = np.split(np.arange(light_users.size), bounds) if nchunk else []
+    streams = rng.spawn(len(parts)) if parts else []
+
+    def one(q: int) -> np.ndarray:
+        idx = parts[q]
+        return _light_pairs(streams[q], light_users[idx], deg[light_users[idx]], cdf, n)
+
+    nw = _workers(workers)
+    if nw > 1 and len(parts) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=nw) as ex:
+            keys.extend(ex.map(one, range(len(parts))))
     else:
-        raise RuntimeError("pair sampler did not converge")
-    keys.append(have)
-    allk = np.concatenate(keys)
-    assert allk.shape[0] == nnz and np.unique(allk).shape[0] == nnz
+        keys.extend(one(q) for q in range(len(parts)))
+    allk = np.concatenate(keys) if keys else np.zeros(0, dtype=np.int64)
+    if allk.shape[0] != nnz:
+        raise RuntimeError("pair sampler drew the wrong count")
     allk = allk[rng.permutation(nnz)]
     return (allk // n).astype(np.int32), (allk % n).astype(np.int32)
 
@@ -141,36 +171,54 @@ def sample_pairs_uniform(m: int, n: int, nnz: int, rng: np.random.Generator):
 # ----------------------------------------------------------------- values
 def planted_values(u: np.ndarray, i: np.ndarray, m: int, n: int, rank: int,
                    sigma_f: float, noise: float, offset: float, rounding: str,
-                   rng: np.random.Generator, chunk: int = 1 << 22) -> np.ndarray:
+                   rng: np.random.Generator, chunk: int = 1 << 21,
+                   workers: Optional[int] = None) -> np.ndarray:
     """offset + <U_u, V_i> + N(0, noise^2), rounded and clipped.
 
     rounding: "int" -> clip(round(y), 1, 5); "half" -> clip(round(2y)/2,
-    0.5, 5); "none" -> y unchanged.  numpy rounds half to even."""
+    0.5, 5); "none" -> y unchanged.  numpy rounds half to even.  The noise of
+    each chunk of ratings comes from its own child stream of ``rng`` (so the
+    result does not depend on ``workers``)."""
+    if rounding not in ("int", "half", "none"):
+        raise ValueError(rounding)
     U = rng.normal(0.0, sigma_f, size=(m, rank)).astype(np.float32)
     V = rng.normal(0.0, sigma_f, size=(n, rank)).astype(np.float32)
     out = np.empty(u.shape[0], dtype=np.float32)
-    for s in range(0, u.shape[0], chunk):
+    starts = list(range(0, u.shape[0], chunk))
+    streams = rng.spawn(len(starts)) if starts else []
+
+    def one(q: int) -> None:
+        s = starts[q]
         e = min(s + chunk, u.shape[0])
         y = np.einsum("ij,ij->i", U[u[s:e]], V[i[s:e]], dtype=np.float64)
         y += offset
         if noise > 0:
-            y += rng.normal(0.0, noise, size=e - s)
+            y += streams[q].normal(0.0, noise, size=e - s)
         if rounding == "int":
             y = np.clip(np.round(y), 1.0, 5.0)
         elif rounding == "half":
             y = np.clip(np.round(2.0 * y) / 2.0, 0.5, 5.0)
-        elif rounding != "none":
-            raise ValueError(rounding)
         out[s:e] = y
+
+    nw = _workers(workers)
+    if nw > 1 and len(starts) > 1:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(max_workers=nw) as ex:
+            list(ex.map(one, range(len(starts))))
+    else:
+        for q in range(len(starts)):
+            one(q)
     return out
 
 
 def split(rat: Ratings, train_frac: float, rng: np.random.Generator):
+    """Seeded random split: the first ``train_frac`` of a random permutation
+    is training data; both parts keep the input order."""
     perm = rng.permutation(len(rat))
     cut = int(round(train_frac * len(rat)))
-    tr = np.sort(perm[:cut])
-    te = np.sort(perm[cut:])
-    return rat.subset(tr), rat.subset(te)
+    train = np.zeros(len(rat), dtype=bool)
+    train[perm[:cut]] = True
+    return rat.subset(np.flatnonzero(train)), rat.subset(np.flatnonzero(~train))
 
 
 # ----------------------------------------------------------------- helpers

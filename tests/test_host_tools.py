@@ -48,6 +48,26 @@ def test_batched_generation_same_with_threads():
         assert np.array_equal(a.train.r, c.train.r)
 
 
+@pytest.mark.parametrize("rounding", ["int", "half"])
+def test_pair_and_value_draws_do_not_depend_on_threads(rounding):
+    """The chunked draws take one child stream per chunk, so the thread
+    count changes nothing; pairs are distinct and degrees follow the caps."""
+    out = []
+    for w in (1, 3):
+        rng = np.random.default_rng(11)
+        u, i = synth.sample_pairs_zipf(5000, 700, 300000, 1.0, 1.1, rng, workers=w)
+        r = synth.planted_values(u, i, 5000, 700, 4, 0.3, 0.5, 3.5, rounding, rng, chunk=40000, workers=w)
+        out.append((u, i, r))
+    for a, c in zip(out[0], out[1]):
+        assert np.array_equal(a, c)
+    u, i, r = out[0]
+    k = u.astype(np.int64) * 700 + i
+    assert np.unique(k).size == k.size == 300000
+    assert np.bincount(u, minlength=5000).max() <= 700 and np.bincount(i, minlength=700).max() <= 5000
+    lo = 1.0 if rounding == "int" else 0.5
+    assert r.min() >= lo and r.max() <= 5.0
+
+
 def brute(u, i, m, n, b, k):
     rb, cb = -(-m // b), -(-n // b)
     users, items = set(), set()

@@ -224,12 +224,23 @@ bmf_status bmf_add_ratings(bmf_ctx *c, int64_t m_new, int64_t n_new, const int32
 bmf_status bmf_fit(bmf_ctx *c, const float hp[8], int32_t max_epochs, double delta, int32_t *epochs_out,
                    double *rmse_out);
 
-/* Order of the strata of epoch `epoch` (b entries). */
+/* Order of the strata of epoch `epoch` (b entries): order[pos] = the
+ * stratum run at position pos, stratum s being the blocks ((j + s) mod b, j)
+ * (Section 3, parallel BMF: the diagonal first, then the blocks below it,
+ * columns wrapping; every block once per iteration).  Mode 0 gives
+ * 0, 1, ..., b-1, mode 1 the seeded shuffle of BMF_OPT_STRATUM_ORDER.
+ * order: caller-allocated host array of b int32.  Host only, no device work.
+ * Errors: BMF_E_INVAL (c or order NULL, epoch < 0). */
 bmf_status bmf_get_schedule(const bmf_ctx *c, int32_t epoch, int32_t *order);
 
-/* The partition of the loaded ratings: block_ptr[b*b + 1] (bucket offsets,
- * block id = row * b + column) and perm[nnz] (perm[pos] = input index of
- * the rating visited at position pos). */
+/* The partition of the loaded ratings into the b x b blocks (Section 3's
+ * block representation, Algorithm 1 steps 1-2; inside a block Algorithm 2's
+ * row-major order): block_ptr[b*b + 1] (bucket offsets into the processing
+ * order, block id = row * b + column, rating t in block (u_t / rb,
+ * i_t / cb)) and perm[nnz] (perm[pos] = input index of the rating visited
+ * at position pos; inside a block (u, i, input index) ascending).  Both are
+ * caller-allocated host arrays; either may be NULL to skip it.  Copies from
+ * the device and synchronises.  Errors: BMF_E_STATE before a load. */
 bmf_status bmf_get_partition(bmf_ctx *c, int64_t *block_ptr, int32_t *perm);
 
 /* Copy the model out (any pointer may be NULL to skip it).  P: m*k, Q: n*k,
@@ -454,6 +465,26 @@ bmf_status bmf_server_get_stats(bmf_server *S, bmf_server_stats *out, int32_t re
 bmf_status bmf_debug_block_plan(int64_t n, const int32_t *u_local, const int32_t *i_local, const float *r,
                                 int32_t cb, int32_t slots, int32_t chunk, int64_t max_steps, int64_t *n_steps,
                                 uint32_t *out);
+
+/* Host-only: the dependency depth of a block's ratings u[x], i[x] (x < n,
+ * in processing order, ids >= 0): the length of the longest chain of
+ * ratings, each sharing its user or its item with the one before it.
+ * Algorithm 2 updates p_u, bu_u, q_i and bi_i at every rating, so the
+ * ratings of such a chain must run one after another and no schedule of
+ * the block (Section 3: a block is factorised by one worker) has fewer
+ * dependent steps.  Errors: BMF_E_INVAL, BMF_E_RANGE (negative id). */
+bmf_status bmf_chain_depth(int64_t n, const int32_t *u, const int32_t *i, int64_t *depth);
+
+/* The dependent-step floor of the LDS-staged SGD kernel on the current
+ * device: one wavefront runs the kernel's own chunk loop (four ratings per
+ * step, Eqs 10-13 on rows in LDS) for `steps` steps (rounded down to whole
+ * chunks of 16) in which every step reads the rows the step before it wrote,
+ * with no staging, barrier or other wavefront.  *ns_per_step receives the
+ * GPU time per step (HIP events around a second launch): the least time a
+ * block's plan can take per dependent step (Algorithm 2's updates of one
+ * block follow each other, Section 3).  k <= 128.  Errors: BMF_E_INVAL,
+ * BMF_E_DEVICE (bmf_last_error(NULL) has the message). */
+bmf_status bmf_debug_chain_floor(int32_t k, int32_t steps, double *ns_per_step);
 
 /* Reduction self-check on the current device: out[0:64], out[64:128],
  * out[128:192] and out[192:256] receive, per lane, the 64-lane sum of

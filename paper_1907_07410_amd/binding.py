@@ -74,6 +74,8 @@ def _load():
         "bmf_foldin": ([p, p, p, i32, i32, f32, f32, p, p], i32),
         "bmf_sgd_timing": ([p, p, p, i32], i32),
         "bmf_debug_wave_sum": ([p, p], i32),
+        "bmf_chain_depth": ([i64, p, p, p], i32),
+        "bmf_debug_chain_floor": ([i32, i32, p], i32),
         "bmf_debug_block_plan": ([i64, p, p, p, i32, i32, i32, i64, p, p], i32),
         "bmf_stratum_order": ([i32, C.c_uint64, i32, i32, p], i32),
         "bmf_batch_create": ([i32, p, p, i32, p, pp], i32),
@@ -321,7 +323,9 @@ class Model:
 
 
 class Batch:
-    """Many problems trained in one persistent launch per epochs call."""
+    """Many independent problems trained together (see bmf_batch_*): one
+    launch per global stratum position runs that position's blocks of every
+    problem that has one; successive positions follow in stream order."""
 
     def __init__(self, shapes, k: int, b=None, seed: Optional[int] = None, order_mode: Optional[int] = None,
                  order_seed: Optional[int] = None, waves: Optional[int] = None):
@@ -497,6 +501,27 @@ def block_plan(u_local, i_local, r, cb: int, slots: int, chunk: int) -> np.ndarr
     if st != 0:
         raise BmfError(st, lib.bmf_last_error(None).decode())
     return out
+
+
+def chain_depth(u, i) -> int:
+    """Dependency depth of a block's ratings in processing order (see
+    bmf_chain_depth; host only)."""
+    u, i = _c(u, np.int32), _c(i, np.int32)
+    out = np.zeros(1, dtype=np.int64)
+    st = lib.bmf_chain_depth(u.shape[0], _ptr(u), _ptr(i), _ptr(out))
+    if st != 0:
+        raise BmfError(st, "bmf_chain_depth")
+    return int(out[0])
+
+
+def chain_floor_ns(k: int, steps: int = 1 << 18) -> float:
+    """GPU time per dependent step of the planned SGD kernel's step code
+    (see bmf_debug_chain_floor)."""
+    out = np.zeros(1, dtype=np.float64)
+    st = lib.bmf_debug_chain_floor(k, steps, _ptr(out))
+    if st != 0:
+        raise BmfError(st, lib.bmf_last_error(None).decode())
+    return float(out[0])
 
 
 def debug_wave_sum(x) -> np.ndarray:

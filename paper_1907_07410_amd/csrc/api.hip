@@ -667,6 +667,49 @@ bmf_status bmf_debug_block_plan(int64_t n, const int32_t *u_local, const int32_t
     return BMF_OK;
 }
 
+bmf_status bmf_debug_chain_floor(int32_t k, int32_t steps, double *ns_per_step) {
+    if (k < 1 || k > 128 || steps < bmf::PLAN_CH || !ns_per_step) return BMF_E_INVAL;
+    hipStream_t s = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float *d = nullptr;
+    bmf_status st = BMF_OK;
+    try {
+        const int chunks = steps / bmf::PLAN_CH;
+        BMF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        BMF_HIP(hipEventCreate(&e0));
+        BMF_HIP(hipEventCreate(&e1));
+        BMF_HIP(hipMalloc(&d, 8 * (128 + 4) * sizeof(float)));
+        bmf::chain_floor(k, chunks, d, s);  // warm-up
+        BMF_HIP(hipEventRecord(e0, s));
+        bmf::chain_floor(k, chunks, d, s);
+        BMF_HIP(hipEventRecord(e1, s));
+        BMF_HIP(hipEventSynchronize(e1));
+        float ms = 0.f;
+        BMF_HIP(hipEventElapsedTime(&ms, e0, e1));
+        *ns_per_step = (double)ms * 1e6 / ((double)chunks * bmf::PLAN_CH);
+    } catch (const Error &e) {
+        g_create_error = e.msg;
+        st = e.code;
+    }
+    if (d) (void)hipFree(d);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (s) (void)hipStreamDestroy(s);
+    return st;
+}
+
+bmf_status bmf_chain_depth(int64_t n, const int32_t *u, const int32_t *i, int64_t *depth) {
+    if (n < 0 || !depth || (n > 0 && (!u || !i))) return BMF_E_INVAL;
+    for (int64_t x = 0; x < n; ++x)
+        if (u[x] < 0 || i[x] < 0) return BMF_E_RANGE;
+    try {
+        *depth = bmf::chain_depth(u, i, n);
+    } catch (const std::bad_alloc &) {
+        return BMF_E_NOMEM;
+    }
+    return BMF_OK;
+}
+
 bmf_status bmf_debug_wave_sum(const float *in64, float *out256) {
     if (!in64 || !out256) return BMF_E_INVAL;
     try {

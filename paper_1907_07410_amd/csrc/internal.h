@@ -230,6 +230,9 @@ void build_partition(Partition &out, const int32_t *u, const int32_t *i, const f
 int plan_kp(int k);
 int plan_slots(int kp, int64_t cb, int CH, int max_lds);
 int64_t plan_block(const uint32_t *ui, int64_t n, int ibits, int cb, int S, int CH, std::vector<PlanEntry> &out);
+// Length of the longest chain of ratings (in processing order) in which each
+// rating shares its user or its item with the one before it.
+int64_t chain_depth(const int32_t *u, const int32_t *i, int64_t n);
 void build_plan(Plan &out, const Partition &part, int b, int k, int max_lds, hipStream_t s);
 // The host part of build_plan: plan the records (host, processing order)
 // into `flat`; false (out.ok false) when the planned kernel does not apply.
@@ -327,5 +330,9 @@ void harvest_timing(Model &M, bool wait);
 // Diagnostics: the three wavefront sums of 64 values (xor butterfly, DPP
 // butterfly, 16-lane row sums) on the device.
 void debug_wave_sum(const float *d_in, float *d_out, hipStream_t s);
+// The planned kernel's dependent-step floor: one wavefront, `chunks` chunks
+// of PLAN_CH steps whose every step depends on the one before; d_out
+// receives 8 (16 F + 4) floats (k <= 128).
+void chain_floor(int k, int chunks, float *d_out, hipStream_t s);
 
 }  // namespace bmf

@@ -157,6 +157,20 @@ int64_t plan_block(const uint32_t *ui, int64_t n, int ibits, int cb, int S, int 
     return (int64_t)out.size() / PLAN_W;
 }
 
+int64_t chain_depth(const int32_t *u, const int32_t *i, int64_t n) {
+    if (n <= 0) return 0;
+    const int32_t umax = *std::max_element(u, u + n), imax = *std::max_element(i, i + n);
+    std::vector<int64_t> du((size_t)umax + 1, 0), di((size_t)imax + 1, 0);
+    int64_t best = 0;
+    for (int64_t x = 0; x < n; ++x) {
+        // one after the last rating of its user and the last of its item
+        const int64_t d = std::max(du[u[x]], di[i[x]]) + 1;
+        du[u[x]] = di[i[x]] = d;
+        best = std::max(best, d);
+    }
+    return best;
+}
+
 int plan_slots(int kp, int64_t cb, int CH, int max_lds) {
     max_lds = std::min(max_lds, PLAN_LDS_BYTES);
     const PlanLds L0 = plan_lds(kp, cb, 0, CH);

@@ -206,6 +206,54 @@ __device__ __forceinline__ void row_st(float *a, const float (&v)[F]) {
     }
 }
 
+// One step of the chain wavefront: lane group g (16 lanes) takes its record
+// rec = {item row LDS offset, rating bits, user slot LDS offset, -}, reads
+// both rows and biases from LDS, sums the dot product over its 16 lanes,
+// applies Eqs 10-13 and writes the rows back.
+template <int F>
+__device__ __forceinline__ void plan_step(unsigned char *smem, const uint4 rec, int gl, float mu, const HP &hp) {
+    constexpr int KP = 16 * F;
+    float *urow = reinterpret_cast<float *>(smem + rec.z);
+    float *qrow = reinterpret_cast<float *>(smem + rec.x);
+    const float bu0 = urow[KP], bi0 = qrow[KP];
+    float p[F], q[F];
+    row_ld<F>(p, urow + gl * F);
+    row_ld<F>(q, qrow + gl * F);
+    const float dot = row16_sum(lane_dot(p, q));
+    const float e = residual(__uint_as_float(rec.y), mu, bu0, bi0, dot);
+    factor_update(p, q, e, hp);
+    row_st<F>(urow + gl * F, p);
+    row_st<F>(qrow + gl * F, q);
+    urow[KP] = bias_update(bu0, e, hp.a_bu, hp.b_bu);
+    qrow[KP] = bias_update(bi0, e, hp.a_bi, hp.b_bi);
+}
+
+// The chain wavefront's loop over one chunk of len steps (records rb, four
+// per step): steps in groups of four (then two, one), so the registers a
+// step writes back from are not the ones the next step loads into.
+template <int F>
+__device__ __forceinline__ void plan_chunk(unsigned char *smem, const SlotRec *rb, int len, int g, int gl, float mu,
+                                           const HP &hp) {
+    int t = 0;
+    for (; t + 3 < len; t += 4) {
+        const uint4 r0 = *reinterpret_cast<const uint4 *>(&rb[t * PLAN_W + g]);
+        const uint4 r1 = *reinterpret_cast<const uint4 *>(&rb[(t + 1) * PLAN_W + g]);
+        const uint4 r2 = *reinterpret_cast<const uint4 *>(&rb[(t + 2) * PLAN_W + g]);
+        const uint4 r3 = *reinterpret_cast<const uint4 *>(&rb[(t + 3) * PLAN_W + g]);
+        plan_step<F>(smem, r0, gl, mu, hp);
+        plan_step<F>(smem, r1, gl, mu, hp);
+        plan_step<F>(smem, r2, gl, mu, hp);
+        plan_step<F>(smem, r3, gl, mu, hp);
+    }
+    for (; t + 1 < len; t += 2) {
+        const uint4 r0 = *reinterpret_cast<const uint4 *>(&rb[t * PLAN_W + g]);
+        const uint4 r1 = *reinterpret_cast<const uint4 *>(&rb[(t + 1) * PLAN_W + g]);
+        plan_step<F>(smem, r0, gl, mu, hp);
+        plan_step<F>(smem, r1, gl, mu, hp);
+    }
+    if (t < len) plan_step<F>(smem, *reinterpret_cast<const uint4 *>(&rb[t * PLAN_W + g]), gl, mu, hp);
+}
+
 __device__ __forceinline__ int lane_rank(uint64_t mask) {
     return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
@@ -335,46 +383,8 @@ __device__ __forceinline__ void planned_block(const SlotRec *__restrict__ steps,
     __syncthreads();
     for (int c = 0; c < nch; ++c) {
         if (wave == 0) {
-            const SlotRec *rb = Rb + (size_t)(c % 3) * RPC;
             const int len = (int)std::min<int64_t>(CH, nsteps - (int64_t)c * CH);
-            // One step: the group's user and item rows (and biases) from
-            // LDS, the update, the rows back to LDS.  Steps go in groups of
-            // four (then two, one): fewer loop instructions, and the
-            // registers a step writes back from are not the ones the next
-            // step loads into, so its loads need not wait for those writes.
-            auto step = [&](const uint4 rec) {
-                float *urow = reinterpret_cast<float *>(smem + rec.z);
-                float *qrow = reinterpret_cast<float *>(smem + rec.x);
-                const float bu0 = urow[KP], bi0 = qrow[KP];
-                float p[F], q[F];
-                row_ld<F>(p, urow + gl * F);
-                row_ld<F>(q, qrow + gl * F);
-                const float dot = row16_sum(lane_dot(p, q));
-                const float e = residual(__uint_as_float(rec.y), mu, bu0, bi0, dot);
-                factor_update(p, q, e, hp);
-                row_st<F>(urow + gl * F, p);
-                row_st<F>(qrow + gl * F, q);
-                urow[KP] = bias_update(bu0, e, hp.a_bu, hp.b_bu);
-                qrow[KP] = bias_update(bi0, e, hp.a_bi, hp.b_bi);
-            };
-            int t = 0;
-            for (; t + 3 < len; t += 4) {
-                const uint4 r0 = *reinterpret_cast<const uint4 *>(&rb[t * PLAN_W + g]);
-                const uint4 r1 = *reinterpret_cast<const uint4 *>(&rb[(t + 1) * PLAN_W + g]);
-                const uint4 r2 = *reinterpret_cast<const uint4 *>(&rb[(t + 2) * PLAN_W + g]);
-                const uint4 r3 = *reinterpret_cast<const uint4 *>(&rb[(t + 3) * PLAN_W + g]);
-                step(r0);
-                step(r1);
-                step(r2);
-                step(r3);
-            }
-            for (; t + 1 < len; t += 2) {
-                const uint4 r0 = *reinterpret_cast<const uint4 *>(&rb[t * PLAN_W + g]);
-                const uint4 r1 = *reinterpret_cast<const uint4 *>(&rb[(t + 1) * PLAN_W + g]);
-                step(r0);
-                step(r1);
-            }
-            if (t < len) step(*reinterpret_cast<const uint4 *>(&rb[t * PLAN_W + g]));
+            plan_chunk<F>(smem, Rb + (size_t)(c % 3) * RPC, len, g, gl, mu, hp);
         } else {
             if (c > 0) write_back(c - 1);
             if (c + 1 < nch) stage(c + 1);
@@ -660,6 +670,43 @@ void harvest_timing(Model &M, bool wait) {
 }
 
 // ------------------------------------------------------------ diagnostics
+// Dependent-step floor of the planned kernel: one wavefront runs the chain
+// wavefront's chunk loop (plan_chunk, the same code) over chunks whose four
+// records per step always name the same user slot and item row per lane
+// group, so every step reads the rows the step before it wrote: a chain of
+// dependent steps with no staging, no barrier and no other wavefront.  Rows
+// start at small values and out[] receives a row so that nothing is
+// optimised away.
+template <int F>
+__global__ __launch_bounds__(64) void chain_floor_kernel(int chunks, float mu, HP hp, float *out) {
+    constexpr int KP = 16 * F, RS = KP + 4;
+    __shared__ __align__(16) unsigned char smem[(8 * RS) * 4 + PLAN_CH * PLAN_W * sizeof(SlotRec)];
+    float *rows = reinterpret_cast<float *>(smem);
+    SlotRec *rb = reinterpret_cast<SlotRec *>(smem + 8 * RS * 4);
+    const int lane = threadIdx.x, g = lane >> 4, gl = lane & 15;
+    for (int x = lane; x < 8 * RS; x += WAVE) rows[x] = 0.01f * (float)((x % 7) + 1);
+    for (int x = lane; x < PLAN_CH * PLAN_W; x += WAVE) {
+        const int gg = x % PLAN_W;
+        rb[x] = SlotRec{(uint32_t)(gg * RS * 4), 3.0f + 0.5f * (float)gg, (uint32_t)((4 + gg) * RS * 4), 0u};
+    }
+    __syncthreads();
+    for (int c = 0; c < chunks; ++c) plan_chunk<F>(smem, rb, PLAN_CH, g, gl, mu, hp);
+    __syncthreads();
+    for (int x = lane; x < 8 * RS; x += WAVE) out[x] = rows[x];
+}
+
+void chain_floor(int k, int chunks, float *d_out, hipStream_t s) {
+    const HP hp{0.005f, 0.05f, 0.005f, 0.05f, 0.005f, 0.05f, 0.005f, 0.05f};
+    switch (plan_kp(k)) {
+    case 16: chain_floor_kernel<1><<<1, 64, 0, s>>>(chunks, 3.5f, hp, d_out); break;
+    case 32: chain_floor_kernel<2><<<1, 64, 0, s>>>(chunks, 3.5f, hp, d_out); break;
+    case 64: chain_floor_kernel<4><<<1, 64, 0, s>>>(chunks, 3.5f, hp, d_out); break;
+    case 128: chain_floor_kernel<8><<<1, 64, 0, s>>>(chunks, 3.5f, hp, d_out); break;
+    default: BMF_FAIL(BMF_E_INVAL, "the planned kernel's step needs k <= 128");
+    }
+    BMF_HIP(hipGetLastError());
+}
+
 __global__ void debug_wave_sum_kernel(const float *in, float *out) {
     const int lane = threadIdx.x;
     const float v = in[lane];

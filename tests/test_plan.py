@@ -154,3 +154,37 @@ def test_plan_empty_and_bad_input():
     with pytest.raises(B.BmfError) as ex:  # item outside the slice
         B.block_plan(np.array([0], np.int32), np.array([8], np.int32), np.ones(1, np.float32), 8, 4, 16)
     assert ex.value.status == B.BMF_E_RANGE
+
+
+def _longest_chain(u, i):
+    """Longest sequence of ratings t1 < t2 < ... in which each shares its
+    user or its item with the one before (every pair examined)."""
+    L = [1] * len(u)
+    for t in range(len(u)):
+        for s in range(t):
+            if (u[s] == u[t] or i[s] == i[t]) and L[s] + 1 > L[t]:
+                L[t] = L[s] + 1
+    return max(L, default=0)
+
+
+def test_chain_depth_matches_pairwise_search():
+    """bmf_chain_depth (the dependency depth of a block under Algorithm 2's
+    order) against an all-pairs search, and the plan never beats it."""
+    rng = np.random.default_rng(8)
+    for trial in range(40):
+        nu, ni = int(rng.integers(1, 9)), int(rng.integers(1, 9))
+        n = int(rng.integers(0, 70))
+        if n:
+            u, i, r = make_block(rng, nu, ni, n)
+        else:
+            u, i, r = np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.float32)
+        d = B.chain_depth(u, i)
+        assert d == _longest_chain(u.tolist(), i.tolist()), trial
+        plan = B.block_plan(u, i, r, ni, 8, 16)
+        assert plan.shape[0] >= max(d, -(-len(u) // 4))
+    # one user's ratings and one item's ratings are chains of their length
+    assert B.chain_depth(np.zeros(30, np.int32), np.arange(30, dtype=np.int32)) == 30
+    assert B.chain_depth(np.arange(25, dtype=np.int32), np.full(25, 3, np.int32)) == 25
+    assert B.chain_depth(np.arange(25, dtype=np.int32), np.arange(25, dtype=np.int32)) == 1
+    with pytest.raises(B.BmfError):
+        B.chain_depth(np.array([-1], np.int32), np.array([0], np.int32))

@@ -1,16 +1,24 @@
-"""Benchmark: stratified block-SGD training of biased MF on the mid-scale
-synthetic workload (138,000 users x 27,000 items, 20M Zipf(1.1) ratings,
-half stars, 90/10 split, k=64, 64 x 64 blocks, lr 0.005, reg 0.05).
+"""Benchmark: stratified block-SGD training of biased MF (the paper's
+Algorithm 1 with Algorithm 2 per block) on one MI355X.
 
-One step = one iteration of the paper's Algorithm 1: one epoch over every
+Headline workload (the largest single-problem configuration): 480,000 users
+x 17,800 items, 100M Zipf(1.0) integer ratings from a planted rank-64 model,
+90/10 split (90M training ratings), k=128, 128 x 128 blocks, lr 0.005,
+reg 0.05.  One step = one iteration of Algorithm 1: one epoch over every
 training rating (b strata of b concurrent blocks) followed by the test RMSE
-(the quantity the stopping rule watches).  value = training rating updates
-per second over the timed steps, inputs resident in HBM.
+(what the stopping rule watches).  value = training rating updates per
+second over the timed steps, inputs resident in HBM.  The run's RMSE after
+the configuration's 20 epochs is compared with the FP64 oracle's
+("matched RMSE").
 
-Also reported: the SGD kernel's achieved algorithmic HBM bandwidth against
-the MI355X peak, the FP64 oracle timed on the host cores on one epoch, the
-one-epoch parity of the GPU factors against that oracle epoch, and top-100
-throughput for a batch of users in FP32 and BF16 scoring.
+Also reported: the SGD stratum kernel against the HBM roof (algorithmic
+bytes per launch over the HIP-event launch time) and against the
+dependency-chain bound it actually runs into (critical plan steps per epoch
+times the measured time of one dependent step), the FP64 oracle timed on the
+host cores, top-100 for every user in FP32 and BF16 scoring, and further
+legs: the mid workload (138,000 x 27,000, 18M training ratings, k=64,
+64 x 64 blocks), serving, batched training, the paper's protocol,
+incremental data and out-of-core training.
 """
 from __future__ import annotations
 
@@ -28,12 +36,12 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}  # MI355X dense matrix peaks
 
-# HBM bytes per launch of the SGD stratum kernel on this workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000: the factors
-# that make the counters match a plain 256 MiB copy kernel), valid for the
-# kernel sources with this sha1; reported as null once they change.
-SGD_TRAFFIC = {"sources_sha1": "0932b6019bd9bef949ea938a91afc3e27e113862",
-               "fetch_bytes": 26925611.8, "write_bytes": 21915844.7}
+# HBM bytes per launch of the SGD stratum kernel per workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), each scaled by the factor
+# that makes the same counter read a plain copy kernel's known bytes; valid
+# for the kernel sources with this sha1 and reported as null once they
+# change.
+SGD_TRAFFIC = {}
 SGD_SOURCES = ["paper_1907_07410_amd/csrc/sgd.hip", "paper_1907_07410_amd/csrc/plan.hip",
                "paper_1907_07410_amd/csrc/plan.h", "paper_1907_07410_amd/csrc/wave.h"]
 
@@ -53,25 +61,36 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def measured_traffic():
+def sources_sha1() -> str:
     import hashlib
     h = hashlib.sha1()
     for f in SGD_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != SGD_TRAFFIC["sources_sha1"]:
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str):
+    t = SGD_TRAFFIC.get(workload)
+    if t is None or t["sources_sha1"] != sources_sha1():
         return None
-    return SGD_TRAFFIC["fetch_bytes"] + SGD_TRAFFIC["write_bytes"]
+    return t["fetch_bytes"] + t["write_bytes"]
 
 
 def algorithmic_bytes(u, i, m, n, b, k):
     """Bytes one epoch must move: every rating record once (8 B), plus, per
     block, each distinct user row and item row (k factors + bias, FP32) read
-    once and written once."""
+    once and written once.  A user's block row is fixed by the user, so the
+    distinct (block, user) pairs are the distinct (user, block column)
+    pairs; likewise for items."""
     rb, cb = -(-m // b), -(-n // b)
-    blk = (u.astype(np.int64) // rb) * b + (i.astype(np.int64) // cb)
-    users = np.unique(blk * m + u).shape[0]
-    items = np.unique(blk * n + i).shape[0]
+    seen = np.zeros(m * b, dtype=bool)
+    seen[u.astype(np.int64) * b + i // cb] = True
+    users = int(np.count_nonzero(seen))
+    del seen
+    seen = np.zeros(n * b, dtype=bool)
+    seen[i.astype(np.int64) * b + u // rb] = True
+    items = int(np.count_nonzero(seen))
     return u.shape[0] * 8 + (users + items) * (k + 1) * 4 * 2, users, items
 
 
@@ -114,10 +133,11 @@ def tables_recall(G, P, Q, bu, bi, mu, K, users, n64=32):
 
 def serving_leg(binding, args):
     """Top-100 serving on the 1M-user x 100k-item, k=128 factor tables:
-    the continuous-batching server scoring in BF16 (FP32 rescoring) against
-    an FP32 server that runs one request at a time.  Each runs the same
-    request stream submitted at once (saturated throughput), then a Poisson
-    stream at half of its own saturated rate (latency at load)."""
+    the continuous-batching server scoring in BF16 (FP32 rescoring), the same
+    server scoring in FP32, and an FP32 server that runs one request at a
+    time.  Each runs the same request stream submitted at once (saturated
+    throughput), then Poisson streams at 10/50/90/120% of its own saturated
+    rate (latency at load); req/s at a stated p99 compares the three."""
     from paper_1907_07410_amd import configs, serving, synth
     sc = configs.SERVING
     t0 = time.time()
@@ -149,7 +169,11 @@ def serving_leg(binding, args):
            "mix": f"{int(sc.topk_frac * 100)}% top-{sc.K} for log-uniform {sc.batch_range} users, "
                   f"rest fold-in of log-uniform {sc.foldin_range} ratings"}
     users = sum(len(r.users) for r in reqs if r.kind == "topk")
+    # three servers on the same streams: BF16 scoring with continuous
+    # batching, FP32 scoring with the same batching (what BF16 adds on its
+    # own), and FP32 one request at a time (the unbatched baseline)
     for name, kw, prec in (("bf16_continuous_batching", dict(), 1),
+                           ("fp32_continuous_batching", dict(), 0),
                            ("fp32_one_request_per_batch", dict(max_batches=1, max_requests_per_batch=1), 0)):
         S = binding.Server(G, mem_budget_bytes=4 << 30, foldin_passes=sc.foldin_passes, foldin_lr=sc.lr,
                            foldin_reg=sc.reg, **kw)
@@ -173,6 +197,17 @@ def serving_leg(binding, args):
         log(f"serving {name}: {sat:.1f} req/s saturated (p99 {st['p99_ms']:.1f} ms); Poisson p99 at 10/50/90/120%: "
             + " / ".join(f"{x['p99_ms']:.2f}" for x in sweep) + " ms")
         S.close()
+    # the largest achieved rate among each server's load points whose p99
+    # stays within a stated latency objective
+    slo = {}
+    for slo_ms in (2.0, 5.0, 10.0):
+        row = {}
+        for name in ("bf16_continuous_batching", "fp32_continuous_batching", "fp32_one_request_per_batch"):
+            ok = [x["achieved_req_per_s"] for x in out[name]["poisson_sweep"] if x["p99_ms"] <= slo_ms]
+            row[name] = max(ok) if ok else None
+        slo[f"p99_le_{slo_ms:g}ms"] = row
+    out["req_per_s_at_p99_slo"] = slo
+    log("serving req/s at p99 <= 5 ms: " + ", ".join(f"{k2} {v}" for k2, v in slo["p99_le_5ms"].items()))
     # fold-in latency alone (host call: upload, 10 passes, download), k = 128
     fold = {}
     frng = np.random.default_rng(args.seed + 13)
@@ -254,15 +289,22 @@ def batched_leg(binding, args, torch):
         same[str(q)] = all(np.array_equal(x.view(np.uint32), y.view(np.uint32)) for x, y in zip(got[:4], want[:4]))
         G.close()
     log(f"batched: train RMSE {min(train_rmse):.4f}-{max(train_rmse):.4f}; alone bit-identical {same}")
+    # algorithmic bytes of an epoch of every problem on its grid (as for one
+    # problem: records once, each distinct row of each block in and out)
+    abytes = sum(algorithmic_bytes(p.train.u, p.train.i, p.m, p.n, g, bc.k)[0] for p, g in zip(probs, grids))
     out = {"problems": len(probs), "scale": args.batched_scale, "ratings": int(sum(nnz)), "k": bc.k,
            "epochs": bc.epochs, "updates_per_s": sum(nnz) * bc.epochs / el, "epoch_ms": el * 1e3 / bc.epochs,
            "kernel_ms_per_epoch": ms / bc.epochs, "launches_per_epoch": launches / bc.epochs,
            "alone_sequential_epoch_ms": alone_ms, "speedup_vs_alone": alone_ms / (ms / bc.epochs),
            "tune_s": tune_s, "waves": waves, "grids": {str(b): grids.count(b) for b in sorted(set(grids))},
            "train_rmse_range": [min(train_rmse), max(train_rmse)],
-           "alone_bit_identical": same}
+           "alone_bit_identical": same,
+           "algorithmic_bytes_per_epoch": abytes,
+           "achieved_GBps": abytes / (ms / bc.epochs / 1e3) / 1e9,
+           "frac_of_hbm_peak": abytes / (ms / bc.epochs / 1e3) / 1e9 / HBM_PEAK_GBS}
     log(f"batched: {out['updates_per_s'] / 1e6:.0f}M updates/s, epoch {out['epoch_ms']:.2f} ms "
-        f"(alone one after another {alone_ms:.2f} ms), grids {out['grids']}, waves {waves}, tune {tune_s:.1f}s")
+        f"(alone one after another {alone_ms:.2f} ms), grids {out['grids']}, waves {waves}, tune {tune_s:.1f}s, "
+        f"{out['achieved_GBps']:.0f} GB/s algorithmic")
     bt.close()
     return out
 
@@ -448,146 +490,51 @@ def out_of_core_leg(binding, args, prob, cfg):
     return out
 
 
-def large_leg(binding, args, torch):
-    """The large-scale workload (480,000 x 17,800, 90M training ratings,
-    k = 128, 128 x 128 blocks): epoch time and SGD roofline, the oracle's
-    first epoch beside it (parity and host time), then top-100 for every
-    user in FP32 and in BF16 with FP32 rescoring (GPU time with events;
-    recall on 20,000 sampled users)."""
-    from paper_1907_07410_amd import configs
-    cfg = configs.LARGE
-    t0 = time.time()
-    prob = cfg.generate(args.seed)
-    tr = prob.train
-    log(f"large: generated {len(tr)} ratings in {time.time() - t0:.1f}s")
-    abytes, _, _ = algorithmic_bytes(tr.u, tr.i, prob.m, prob.n, cfg.b, cfg.k)
-    G = binding.Model(prob.m, prob.n, cfg.k, cfg.b, seed=args.seed + 1000, order_mode=0)
-    t0 = time.perf_counter()
-    G.load_ratings(tr.u, tr.i, tr.r)
-    load_s = time.perf_counter() - t0
-    G.epoch(cfg.lr, cfg.reg)
-    G.synchronize()
-    out = {"workload": f"{prob.m} x {prob.n}, {len(tr)} training ratings, k={cfg.k}, {cfg.b}x{cfg.b} blocks",
-           "load_s": load_s}
-    if not args.no_cpu_baseline:
-        import oracle
-        threads = max(1, min(len(os.sched_getaffinity(0)), 64))
-        O = oracle.Model(prob.m, prob.n, cfg.k, cfg.b, seed=args.seed + 1000, order_mode=0)
-        O.load(tr.u, tr.i, tr.r)
-        t0 = time.perf_counter()
-        O.epoch(cfg.lr, cfg.reg, threads=threads)
-        o_s = time.perf_counter() - t0
-        P, Q, bu, bi, _ = G.get_factors()
-        out["parity_1epoch_max_abs"] = float(max(np.abs(P - O.P).max(), np.abs(Q - O.Q).max(),
-                                                 np.abs(bu - O.bu).max(), np.abs(bi - O.bi).max()))
-        out["oracle_epoch_s"] = o_s
-        out["oracle_updates_per_s"] = len(tr) / o_s
-        out["oracle_threads"] = threads
-        del O, P, Q
-    G.sgd_timing(reset=True)
-    epochs = 3
-    G.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(epochs):
-        G.epoch(cfg.lr, cfg.reg)
-    G.synchronize()
-    el = time.perf_counter() - t0
-    ms, launches = G.sgd_timing(reset=True)
-    per_launch = ms / launches
-    out.update({"updates_per_s": len(tr) * epochs / el, "ms_per_epoch": el / epochs * 1e3,
-                "avg_launch_ms": per_launch, "algorithmic_bytes_per_epoch": abytes,
-                "achieved_GBps": abytes / cfg.b / (per_launch / 1e3) / 1e9})
-    out["frac_of_hbm_peak"] = out["achieved_GBps"] / HBM_PEAK_GBS
-    log(f"large: {out['updates_per_s'] / 1e6:.0f}M updates/s, {out['ms_per_epoch']:.1f} ms/epoch, "
-        f"{per_launch:.3f} ms per stratum, {out['achieved_GBps']:.0f} GB/s algorithmic")
-    # top-100 for every user
-    users = torch.arange(prob.m, dtype=torch.int32, device="cuda")
-    ts = torch.cuda.Stream()
-    G.set_option(binding.OPT_STREAM, ts.cuda_stream)
-    flops = 2.0 * prob.m * prob.n * cfg.k
-    res = {}
-    for name, prec, peak in (("fp32", 0, MFMA_PEAK_TFLOPS["fp32"]), ("bf16", 1, MFMA_PEAK_TFLOPS["bf16"])):
-        it = torch.empty((prob.m, 100), dtype=torch.int32, device="cuda")
-        sc = torch.empty((prob.m, 100), dtype=torch.float32, device="cuda")
-        G.topk_dev(users, 100, prec, 0, it, sc)
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record(ts)
-        G.topk_dev(users, 100, prec, 0, it, sc)
-        ev1.record(ts)
-        ts.synchronize()
-        dt = ev0.elapsed_time(ev1) / 1e3
-        res[name] = it[:20000].cpu().numpy()
-        out[f"topk_all_users_{name}_ms"] = dt * 1e3
-        out[f"topk_all_users_{name}_tflops"] = flops / dt / 1e12
-        out[f"topk_all_users_{name}_frac_of_mfma_peak"] = flops / dt / 1e12 / peak
-        del it, sc
-    G.set_option(binding.OPT_STREAM, 0)
-    out["recall_at_100_bf16_vs_fp32_20k_users"] = float(
-        np.mean([len(set(a) & set(b)) / 100 for a, b in zip(res["fp32"], res["bf16"])]))
-    log(f"large: top-100 for all {prob.m} users FP32 {out['topk_all_users_fp32_ms']:.1f} ms, BF16 "
-        f"{out['topk_all_users_bf16_ms']:.1f} ms, recall {out['recall_at_100_bf16_vs_fp32_20k_users']:.4f}")
-    del G
-    return out
+def block_depths(u, i, m, n, b, perm, bp, binding):
+    """Dependency depth of every block (bmf_chain_depth on the block's
+    ratings in processing order, local ids), as a b x b array."""
+    rb, cb = -(-m // b), -(-n // b)
+    out = np.zeros(b * b, dtype=np.int64)
+    up, ip = u[perm], i[perm]
+    for q in range(b * b):
+        a, e = int(bp[q]), int(bp[q + 1])
+        if e > a:
+            br, bc = divmod(q, b)
+            out[q] = binding.chain_depth(up[a:e] - br * rb, ip[a:e] - bc * cb)
+    return out.reshape(b, b)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--topk-users", type=int, default=4096)
-    ap.add_argument("--sgd-kernel", type=int, default=0)
-    ap.add_argument("--serving-requests", type=int, default=1000,
-                    help="requests per serving measurement (0 skips the serving leg)")
-    ap.add_argument("--batched-scale", type=float, default=1.0,
-                    help="linear scale of the 64-problem batched workload's m and n (0 skips the batched leg)")
-    ap.add_argument("--no-paper-protocol", action="store_true",
-                    help="skip the MovieLens-1M-shaped early-termination leg")
-    ap.add_argument("--no-out-of-core", action="store_true", help="skip the out-of-core leg")
-    ap.add_argument("--large", action="store_true",
-                    help="also run the large-scale leg (90M ratings, k=128; about two more minutes)")
-    ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="also run a plain device copy of this many MiB (reference for HBM traffic counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py measures one GPU only (there is no multi-GPU path); run with --gpus 1", file=sys.stderr)
-        sys.exit(2)
-    if args.warmup < 1:
-        args.warmup = 1
+def stratum_sum_of_max(x, b):
+    """Sum over strata s of the largest entry of blocks ((j + s) mod b, j)."""
+    return int(sum(max(int(x[(j + s) % b, j]) for j in range(b)) for s in range(b)))
 
-    import torch
-    from paper_1907_07410_amd import binding, configs
 
-    assert torch.cuda.is_available(), "bench needs a GPU"
-    torch.cuda.set_device(0)
-    cfg = configs.MID
+def train_leg(binding, args, torch, cfg, steps, warmup, cpu_epochs, copy_gbps):
+    """One configuration trained and timed: load, a warm-up epoch compared
+    with the oracle's first epoch, `steps` timed steps (epoch + test RMSE on
+    device-resident test ratings), the HBM and dependency-chain views of the
+    SGD stratum kernel, the oracle's epochs on the host cores (the CPU
+    baseline), and a second GPU model trained the configuration's epochs whose
+    test RMSE is compared with the oracle's after the same epochs."""
     t0 = time.time()
     prob = cfg.generate(args.seed)
     tr, te = prob.train, prob.test
-    log(f"generated {len(tr)} train / {len(te)} test ratings in {time.time() - t0:.1f}s")
+    log(f"{cfg.name}: generated {len(tr)} train / {len(te)} test ratings in {time.time() - t0:.1f}s")
     abytes, nu_blk, ni_blk = algorithmic_bytes(tr.u, tr.i, prob.m, prob.n, cfg.b, cfg.k)
     cp, maxblk, meanblk = critical_path(tr.u, tr.i, prob.m, prob.n, cfg.b)
-    log(f"algorithmic bytes/epoch {abytes / 1e9:.3f} GB; critical path {cp} ratings")
-
+    log(f"{cfg.name}: algorithmic bytes/epoch {abytes / 1e9:.3f} GB; largest blocks {cp} ratings per epoch")
     G = binding.Model(prob.m, prob.n, cfg.k, cfg.b, seed=args.seed + 1000, order_mode=0,
                       order_seed=args.seed + 2000, sgd_kernel=args.sgd_kernel)
     t0 = time.time()
     G.load_ratings(tr.u, tr.i, tr.r)
     load_s = time.time() - t0
-    log(f"load + partition {load_s:.2f}s")
-
-    # first warm-up epoch, then compare with the oracle's first epoch
+    log(f"{cfg.name}: load + partition + plan {load_s:.2f}s")
     G.epoch(cfg.lr, cfg.reg)
     G.synchronize()
-    parity = None
-    cpu = None
-    match = None
-    if not args.no_cpu_baseline:
+    parity = cpu = match = None
+    threads = max(1, min(len(os.sched_getaffinity(0)), 64))
+    if cpu_epochs > 0:
         import oracle
-        threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-        threads = max(1, min(threads, 64))
         O = oracle.Model(prob.m, prob.n, cfg.k, cfg.b, seed=args.seed + 1000, order_mode=0)
         O.load(tr.u, tr.i, tr.r)
         t0 = time.time()
@@ -596,43 +543,32 @@ def main():
         P, Q, bu, bi, mu = G.get_factors()
         parity = float(max(np.abs(P - O.P).max(), np.abs(Q - O.Q).max(), np.abs(bu - O.bu).max(),
                            np.abs(bi - O.bi).max()))
-        log(f"oracle epoch {first_s:.1f}s on {threads} threads; 1-epoch max abs diff {parity:.3g}")
-        # the rest of the configuration's epochs on both sides: matched RMSE
+        del P, Q
+        log(f"{cfg.name}: oracle epoch {first_s:.1f}s on {threads} threads; 1-epoch max abs diff {parity:.3g}")
+        # the configuration's epochs on both sides: matched RMSE
         G2 = binding.Model(prob.m, prob.n, cfg.k, cfg.b, seed=args.seed + 1000, order_mode=0)
         G2.load_ratings(tr.u, tr.i, tr.r)
         for _ in range(cfg.epochs):
             G2.epoch(cfg.lr, cfg.reg)
         t0 = time.time()
-        for _ in range(cfg.epochs - 1):
+        for _ in range(cpu_epochs - 1):
             O.epoch(cfg.lr, cfg.reg, threads=threads)
         cpu_s = first_s + time.time() - t0
-        g_te, o_te = G2.rmse(te.u, te.i, te.r), O.rmse(te.u, te.i, te.r)
-        g_tr, o_tr = G2.rmse(), O.rmse()
-        match = {"epochs": cfg.epochs, "gpu_test_rmse": g_te, "oracle_test_rmse": o_te,
-                 "gpu_train_rmse": g_tr, "oracle_train_rmse": o_tr,
-                 "max_abs_diff": max(abs(g_te - o_te), abs(g_tr - o_tr)),
-                 "matched": bool(max(abs(g_te - o_te), abs(g_tr - o_tr)) <= 1e-3)}
-        log(f"{cfg.epochs} epochs: test rmse gpu {g_te:.5f} oracle {o_te:.5f}; train gpu {g_tr:.5f} oracle {o_tr:.5f}")
+        if cpu_epochs == cfg.epochs:
+            g_te, o_te = G2.rmse(te.u, te.i, te.r), O.rmse(te.u, te.i, te.r)
+            match = {"epochs": cfg.epochs, "gpu_test_rmse": g_te, "oracle_test_rmse": o_te,
+                     "abs_diff": abs(g_te - o_te), "matched": bool(abs(g_te - o_te) <= 1e-3)}
+            log(f"{cfg.name}: {cfg.epochs} epochs test rmse gpu {g_te:.6f} oracle {o_te:.6f}")
         del O, G2
-        # one epoch of the single-threaded oracle
-        O1 = oracle.Model(prob.m, prob.n, cfg.k, cfg.b, seed=args.seed + 1000, order_mode=0)
-        O1.load(tr.u, tr.i, tr.r)
-        t0 = time.time()
-        O1.epoch(cfg.lr, cfg.reg, threads=1)
-        one_s = time.time() - t0
-        del O1
-        cpu = {"value": len(tr) * cfg.epochs / cpu_s, "unit": "rating updates/s", "cores": threads,
+        cpu = {"value": len(tr) * cpu_epochs / cpu_s, "unit": "rating updates/s", "cores": threads,
                "kind": "oracle", "cpu_model": cpu_model(),
-               "sample": f"{cfg.epochs} full epochs of the mid-scale workload ({len(tr)} updates each, FP64, "
-                         f"{threads} threads over each stratum's blocks), {cpu_s:.1f}s",
-               "single_thread_value": len(tr) / one_s,
-               "single_thread_sample": f"one epoch with one thread, {one_s:.1f}s"}
-        log(f"oracle: {cfg.epochs} epochs {cpu_s:.1f}s on {threads} threads; one epoch single-threaded {one_s:.1f}s")
-    for _ in range(args.warmup - 1):
+               "sample": f"{cpu_epochs} full epochs of this workload ({len(tr)} updates each, FP64, "
+                         f"{threads} threads over each stratum's blocks), {cpu_s:.1f}s"}
+        log(f"{cfg.name}: oracle {cpu_epochs} epochs {cpu_s:.1f}s on {threads} threads")
+    for _ in range(warmup - 1):
         G.epoch(cfg.lr, cfg.reg)
     G.synchronize()
     G.sgd_timing(reset=True)
-
     # test ratings resident on the device for the timed steps
     tu = torch.from_numpy(te.u).cuda()
     ti = torch.from_numpy(te.i).cuda()
@@ -640,36 +576,43 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rmse = None
-    for _ in range(args.steps):
+    for _ in range(steps):
         G.epoch(cfg.lr, cfg.reg)
         rmse = G.rmse_dev(tu, ti, tr_)
     G.synchronize()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     sgd_ms, launches = G.sgd_timing(reset=True)
-    value = len(tr) * args.steps / el
     per_launch_ms = sgd_ms / max(1, launches)
     achieved = (abytes / cfg.b) / (per_launch_ms / 1e3) / 1e9
-    log(f"{args.steps} steps in {el:.3f}s; sgd kernels {sgd_ms:.2f} ms over {launches} launches; test rmse {rmse:.4f}")
+    log(f"{cfg.name}: {steps} steps in {el:.3f}s ({len(tr) * steps / el / 1e6:.0f}M updates/s); sgd kernels "
+        f"{sgd_ms:.2f} ms over {launches} launches ({per_launch_ms * 1e3:.1f} us each); test rmse {rmse:.4f}")
     # the dependency-chain view of the same launches: every block runs its
     # plan's steps (four independent ratings each) one after another, and a
-    # stratum lasts as long as its longest block
+    # stratum lasts as long as its longest block; the floor is the time of one
+    # dependent step of the same step code alone on one wavefront
     kern, plan_steps, slots, blk_steps = G.plan_info(per_block=True)
-    crit_steps = int(sum(max(blk_steps[(j + s) % cfg.b, j] for j in range(cfg.b)) for s in range(cfg.b)))
-    epoch_kernel_ms = sgd_ms / max(1, launches) * cfg.b
+    crit_steps = stratum_sum_of_max(blk_steps, cfg.b)
+    bp, perm = G.get_partition(len(tr))
+    depth = block_depths(tr.u, tr.i, prob.m, prob.n, cfg.b, perm, bp, binding)
+    dag = stratum_sum_of_max(depth, cfg.b)
+    floor_ns = binding.chain_floor_ns(cfg.k)
+    epoch_kernel_ms = per_launch_ms * cfg.b
     chain = {"kernel": kern, "plan_steps_per_epoch": plan_steps, "ratings_per_step": len(tr) / max(1, plan_steps),
              "lds_user_slots": slots, "critical_steps_per_epoch": crit_steps,
+             "dependency_depth_per_epoch": dag, "floor_ns_per_step": floor_ns,
+             "floor_ms_per_epoch": crit_steps * floor_ns / 1e6,
+             "depth_floor_ms_per_epoch": dag * floor_ns / 1e6,
+             "kernel_ms_per_epoch": epoch_kernel_ms,
              "ns_per_critical_step": epoch_kernel_ms * 1e6 / max(1, crit_steps),
-             "cycles_per_critical_step_at_2p4GHz": epoch_kernel_ms * 1e-3 * 2.4e9 / max(1, crit_steps)}
-    log(f"chain: {crit_steps} critical steps per epoch, {chain['ns_per_critical_step']:.0f} ns "
-        f"({chain['cycles_per_critical_step_at_2p4GHz']:.0f} cycles) each")
-
-    # test-RMSE pass alone, timed with events on torch's stream (the
-    # library's stream is pointed at it): algorithmic bytes = the COO once
-    # (12 B) plus the user and item rows with biases ((k+1) 4 B each) per
-    # rating
+             "frac": crit_steps * floor_ns / 1e6 / epoch_kernel_ms}
+    log(f"{cfg.name}: chain {crit_steps} critical plan steps per epoch (dependency depth {dag}), "
+        f"{chain['ns_per_critical_step']:.0f} ns each against a {floor_ns:.0f} ns dependent-step floor")
+    # test-RMSE pass alone, timed with events on a named stream the library
+    # enqueues on: algorithmic bytes = the COO once (12 B) plus the user and
+    # item rows with biases ((k+1) 4 B each) per rating
     G.synchronize()
-    ts = torch.cuda.Stream()  # a named stream: the library and the events share it
+    ts = torch.cuda.Stream()
     G.set_option(binding.OPT_STREAM, ts.cuda_stream)
     G.rmse_dev(tu, ti, tr_)
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -686,81 +629,138 @@ def main():
                 "frac_of_hbm_peak": rmse_bytes / (rmse_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
                 "note": "includes the device range check and the FP64 partial-sum tree"}
     G.set_option(binding.OPT_STREAM, 0)
-    log(f"test RMSE pass {rmse_ms:.3f} ms, {rmse_out['achieved_GBps']:.0f} GB/s algorithmic")
+    log(f"{cfg.name}: test RMSE pass {rmse_ms:.3f} ms, {rmse_out['achieved_GBps']:.0f} GB/s algorithmic")
+    out = {"workload": f"{cfg.name}: {prob.m} users x {prob.n} items, {len(tr)} training ratings, k={cfg.k}, "
+                       f"{cfg.b}x{cfg.b} blocks, lr {cfg.lr}, reg {cfg.reg}",
+           "m": prob.m, "n": prob.n, "n_train": len(tr), "n_test": len(te), "k": cfg.k, "b": cfg.b,
+           "updates_per_s": len(tr) * steps / el, "ms_per_step": el / steps * 1e3, "steps": steps,
+           "rmse_test": rmse, "parity_1epoch_max_abs": parity, "rmse_match": match, "cpu_baseline": cpu,
+           "load_s": load_s, "largest_blocks_ratings_per_epoch": cp, "block_ratings_max": maxblk,
+           "block_ratings_mean": meanblk,
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg.name),
+                        "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
+                        "kernel": "sgd stratum kernel (sgd_plan_kernel)", "algorithmic_bytes_per_launch": abytes / cfg.b,
+                        "algorithmic_bytes_per_epoch": abytes, "avg_launch_ms": per_launch_ms,
+                        "copy_kernel_GBps": copy_gbps, "chain": chain},
+           "rmse_pass": rmse_out}
+    return out, G, prob
 
-    # top-100 for a batch of users, FP32 and BF16 scoring
+
+def topk_all_users(binding, torch, G, prob, cfg):
+    """Top-100 for every user in FP32 and in BF16 with FP32 rescoring (GPU
+    time with events on the library's stream; contraction FLOPs 2 m n k
+    against the MI355X dense matrix peak of each precision), and BF16 recall
+    against FP32 on 20,000 of the users."""
+    users = torch.arange(prob.m, dtype=torch.int32, device="cuda")
+    ts = torch.cuda.Stream()
+    G.set_option(binding.OPT_STREAM, ts.cuda_stream)
+    flops = 2.0 * prob.m * prob.n * cfg.k
+    res = {}
+    out = {"users": prob.m, "items": prob.n, "k": cfg.k, "K": 100, "contraction_flop": flops}
+    for name, prec, peak in (("fp32", 0, MFMA_PEAK_TFLOPS["fp32"]), ("bf16", 1, MFMA_PEAK_TFLOPS["bf16"])):
+        it = torch.empty((prob.m, 100), dtype=torch.int32, device="cuda")
+        sc = torch.empty((prob.m, 100), dtype=torch.float32, device="cuda")
+        G.topk_dev(users, 100, prec, 0, it, sc)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record(ts)
+        G.topk_dev(users, 100, prec, 0, it, sc)
+        ev1.record(ts)
+        ts.synchronize()
+        dt = ev0.elapsed_time(ev1) / 1e3
+        res[name] = it[:20000].cpu().numpy()
+        out[f"{name}_ms"] = dt * 1e3
+        out[f"{name}_users_per_s"] = prob.m / dt
+        out[f"{name}_tflops"] = flops / dt / 1e12
+        out[f"{name}_frac_of_mfma_peak"] = flops / dt / 1e12 / peak
+        del it, sc
+    G.set_option(binding.OPT_STREAM, 0)
+    out["recall_at_100_bf16_vs_fp32_20k_users"] = float(
+        np.mean([len(set(a) & set(b)) / 100 for a, b in zip(res["fp32"], res["bf16"])]))
+    log(f"{cfg.name}: top-100 for all {prob.m} users FP32 {out['fp32_ms']:.1f} ms "
+        f"({out['fp32_frac_of_mfma_peak'] * 100:.1f}% of peak), BF16 {out['bf16_ms']:.1f} ms "
+        f"({out['bf16_frac_of_mfma_peak'] * 100:.1f}%), recall {out['recall_at_100_bf16_vs_fp32_20k_users']:.6f}")
+    return out
+
+
+def topk_batch(binding, torch, G, prob, cfg, nusers, seed):
+    """Top-100 for a batch of users in FP32 and BF16 scoring (GPU time with
+    events), recall of BF16 against FP32 and of both against FP64 scores of
+    the same factors on 64 of the users, and one small request's latency."""
+    rng = np.random.default_rng(seed)
+    users = rng.integers(0, prob.m, nusers).astype(np.int32)
     topk = {}
-    if args.topk_users > 0:
-        rng = np.random.default_rng(7)
-        users = rng.integers(0, prob.m, args.topk_users).astype(np.int32)
-        res = {}
-        du = torch.from_numpy(users).cuda()
+    res = {}
+    du = torch.from_numpy(users).cuda()
+    torch.cuda.synchronize()
+    ts = torch.cuda.Stream()
+    G.set_option(binding.OPT_STREAM, ts.cuda_stream)
+    flops = 2.0 * len(users) * prob.n * cfg.k
+    for name, prec, peak in (("fp32", 0, MFMA_PEAK_TFLOPS["fp32"]), ("bf16", 1, MFMA_PEAK_TFLOPS["bf16"])):
+        it = torch.empty((len(users), 100), dtype=torch.int32, device="cuda")
+        sc = torch.empty((len(users), 100), dtype=torch.float32, device="cuda")
         torch.cuda.synchronize()
-        G.set_option(binding.OPT_STREAM, ts.cuda_stream)
-        flops = 2.0 * len(users) * prob.n * cfg.k
-        for name, prec, peak in (("fp32", 0, MFMA_PEAK_TFLOPS["fp32"]), ("bf16", 1, MFMA_PEAK_TFLOPS["bf16"])):
-            it = torch.empty((len(users), 100), dtype=torch.int32, device="cuda")
-            sc = torch.empty((len(users), 100), dtype=torch.float32, device="cuda")
-            torch.cuda.synchronize()
+        G.topk_dev(du, 100, prec, 0, it, sc)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        ev0.record(ts)
+        for _ in range(reps):
             G.topk_dev(du, 100, prec, 0, it, sc)
+        ev1.record(ts)
+        ts.synchronize()
+        dt = ev0.elapsed_time(ev1) / reps / 1e3
+        res[name] = (it.cpu().numpy(), sc.cpu().numpy())
+        topk[name + "_users_per_s"] = len(users) / dt
+        topk[name + "_ms"] = dt * 1e3
+        topk[name + "_contraction_tflops"] = flops / dt / 1e12
+        topk[name + "_frac_of_mfma_peak"] = flops / dt / 1e12 / peak
+    G.set_option(binding.OPT_STREAM, 0)
+    topk["recall_at_100_bf16_vs_fp32"] = float(
+        np.mean([len(set(a) & set(b)) / 100 for a, b in zip(res["fp32"][0], res["bf16"][0])]))
+    P, Q, bu, bi, mu = G.get_factors()
+    Qd, bid = Q.astype(np.float64), bi.astype(np.float64)
+    rec = {"fp32": [], "bf16": []}
+    err = {"fp32": 0.0, "bf16": 0.0}
+    for row in range(64):
+        uu = users[row]
+        s64 = mu + float(bu[uu]) + bid + Qd @ P[uu].astype(np.float64)
+        best = set(np.argsort(-s64, kind="stable")[:100].tolist())
+        for name in ("fp32", "bf16"):
+            its, scs = res[name][0][row], res[name][1][row]
+            rec[name].append(len(best & set(its.tolist())) / 100)
+            err[name] = max(err[name], float(np.abs(scs.astype(np.float64) - s64[its]).max()))
+    for name in ("fp32", "bf16"):
+        topk[f"recall_at_100_{name}_vs_fp64"] = float(np.mean(rec[name]))
+        topk[f"max_score_error_{name}_vs_fp64"] = err[name]
+    topk["users"] = len(users)
+    topk["items"] = prob.n
+    small = {}
+    G.set_option(binding.OPT_STREAM, ts.cuda_stream)
+    for nb in (1, 16, 64):
+        du_s = du[:nb].contiguous()
+        it = torch.empty((nb, 100), dtype=torch.int32, device="cuda")
+        sc = torch.empty((nb, 100), dtype=torch.float32, device="cuda")
+        row = {}
+        for name, prec in (("fp32", 0), ("bf16", 1)):
+            G.topk_dev(du_s, 100, prec, 0, it, sc)
             ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            reps = 5
             ev0.record(ts)
-            for _ in range(reps):
-                G.topk_dev(du, 100, prec, 0, it, sc)
+            for _ in range(10):
+                G.topk_dev(du_s, 100, prec, 0, it, sc)
             ev1.record(ts)
             ts.synchronize()
-            dt = ev0.elapsed_time(ev1) / reps / 1e3
-            res[name] = (it.cpu().numpy(), sc.cpu().numpy())
-            topk[name + "_users_per_s"] = len(users) / dt
-            topk[name + "_ms"] = dt * 1e3
-            topk[name + "_contraction_tflops"] = flops / dt / 1e12
-            topk[name + "_frac_of_mfma_peak"] = flops / dt / 1e12 / peak
-        G.set_option(binding.OPT_STREAM, 0)
-        recall = float(np.mean([len(set(a) & set(b)) / 100 for a, b in zip(res["fp32"][0], res["bf16"][0])]))
-        topk["recall_at_100_bf16_vs_fp32"] = recall
-        # against FP64 scores of the same factors, on 64 of the users
-        P, Q, bu, bi, mu = G.get_factors()
-        Qd, bid = Q.astype(np.float64), bi.astype(np.float64)
-        rec = {"fp32": [], "bf16": []}
-        err = {"fp32": 0.0, "bf16": 0.0}
-        for row in range(64):
-            uu = users[row]
-            s64 = mu + float(bu[uu]) + bid + Qd @ P[uu].astype(np.float64)
-            best = set(np.argsort(-s64, kind="stable")[:100].tolist())
-            for name in ("fp32", "bf16"):
-                its, scs = res[name][0][row], res[name][1][row]
-                rec[name].append(len(best & set(its.tolist())) / 100)
-                err[name] = max(err[name], float(np.abs(scs.astype(np.float64) - s64[its]).max()))
-        for name in ("fp32", "bf16"):
-            topk[f"recall_at_100_{name}_vs_fp64"] = float(np.mean(rec[name]))
-            topk[f"max_score_error_{name}_vs_fp64"] = err[name]
-        topk["users"] = len(users)
-        topk["items"] = prob.n
-        # small batches: latency of one request (GPU time with events)
-        small = {}
-        G.set_option(binding.OPT_STREAM, ts.cuda_stream)
-        for nb in (1, 16, 64):
-            du_s = du[:nb].contiguous()
-            it = torch.empty((nb, 100), dtype=torch.int32, device="cuda")
-            sc = torch.empty((nb, 100), dtype=torch.float32, device="cuda")
-            row = {}
-            for name, prec in (("fp32", 0), ("bf16", 1)):
-                G.topk_dev(du_s, 100, prec, 0, it, sc)
-                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                ev0.record(ts)
-                for _ in range(10):
-                    G.topk_dev(du_s, 100, prec, 0, it, sc)
-                ev1.record(ts)
-                ts.synchronize()
-                row[name + "_ms"] = ev0.elapsed_time(ev1) / 10
-            small[str(nb)] = row
-        G.set_option(binding.OPT_STREAM, 0)
-        topk["small_batches"] = small
+            row[name + "_ms"] = ev0.elapsed_time(ev1) / 10
+        small[str(nb)] = row
+    G.set_option(binding.OPT_STREAM, 0)
+    topk["small_batches"] = small
+    log(f"{cfg.name}: top-100 for {len(users)} users FP32 {topk['fp32_ms']:.3f} ms, BF16 {topk['bf16_ms']:.3f} ms, "
+        f"recall {topk['recall_at_100_bf16_vs_fp32']:.4f}")
+    return topk
 
-    del G
-    ooc_out = None if args.no_out_of_core else out_of_core_leg(binding, args, prob, cfg)
-    # plain device copy for the bandwidth the chip delivers to a streaming kernel
+
+def copy_bandwidth(torch):
+    """A plain device copy (1 GiB read + 1 GiB written): the streaming rate
+    the chip delivers next to the datasheet peak."""
     xb = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
     yb = torch.empty_like(xb)
     yb.copy_(xb)
@@ -770,14 +770,72 @@ def main():
         yb.copy_(xb)
     ev1.record()
     torch.cuda.synchronize()
-    copy_gbps = 2 * xb.numel() * 4 * 5 / (ev0.elapsed_time(ev1) / 1e3) / 1e9
+    gbps = 2 * xb.numel() * 4 * 5 / (ev0.elapsed_time(ev1) / 1e3) / 1e9
     del xb, yb
-    log(f"device copy (1 GiB read + 1 GiB written): {copy_gbps:.0f} GB/s")
+    log(f"device copy (1 GiB read + 1 GiB written): {gbps:.0f} GB/s")
+    return gbps
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--topk-users", type=int, default=4096, help="users of the mid workload's top-K batch (0 skips)")
+    ap.add_argument("--sgd-kernel", type=int, default=0)
+    ap.add_argument("--serving-requests", type=int, default=1000,
+                    help="requests per serving measurement (0 skips the serving leg)")
+    ap.add_argument("--batched-scale", type=float, default=1.0,
+                    help="linear scale of the 64-problem batched workload's m and n (0 skips the batched leg)")
+    ap.add_argument("--no-paper-protocol", action="store_true",
+                    help="skip the MovieLens-1M-shaped early-termination and incremental legs")
+    ap.add_argument("--no-out-of-core", action="store_true", help="skip the out-of-core leg")
+    ap.add_argument("--no-mid", action="store_true", help="skip the mid workload's leg (and the out-of-core leg)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="the headline workload's leg alone (for profiling runs)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this many MiB (reference for HBM traffic counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only (there is no multi-GPU path); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.warmup < 1:
+        args.warmup = 1
+    if args.headline_only:
+        args.no_mid = args.no_out_of_core = args.no_paper_protocol = True
+        args.serving_requests = 0
+        args.batched_scale = 0.0
+
+    import torch
+    from paper_1907_07410_amd import binding, configs
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    copy_gbps = copy_bandwidth(torch)
+    cfg = configs.LARGE
+    cpu_epochs = 0 if args.no_cpu_baseline else cfg.epochs
+    head, G, prob = train_leg(binding, args, torch, cfg, args.steps, args.warmup, cpu_epochs, copy_gbps)
+    head["topk_all_users"] = topk_all_users(binding, torch, G, prob, cfg)
+    G.close()
+    del G, prob
+    mid = None
+    ooc_out = None
+    if not args.no_mid:
+        mcfg = configs.MID
+        mid, Gm, mprob = train_leg(binding, args, torch, mcfg, args.steps, 1,
+                                   0 if args.no_cpu_baseline else mcfg.epochs, copy_gbps)
+        if args.topk_users > 0:
+            mid["topk"] = topk_batch(binding, torch, Gm, mprob, mcfg, args.topk_users, 7)
+        Gm.close()
+        del Gm
+        ooc_out = None if args.no_out_of_core else out_of_core_leg(binding, args, mprob, mcfg)
+        del mprob
     serving_out = serving_leg(binding, args) if args.serving_requests > 0 else None
     batched_out = batched_leg(binding, args, torch) if args.batched_scale > 0 else None
     paper_out = None if args.no_paper_protocol else paper_leg(binding, args)
     incr_out = None if args.no_paper_protocol else incremental_leg(binding, args)
-    large_out = large_leg(binding, args, torch) if args.large else None
     if args.copy_calibration_mib > 0:
         nbytes = args.copy_calibration_mib << 20
         x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
@@ -790,41 +848,34 @@ def main():
 
     line = {
         "metric": "rating updates/s at matched RMSE; top-100 req/s + p99 latency (BF16 vs FP32)",
-        "value": value,
+        "value": head["updates_per_s"],
         "unit": "rating updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": el / args.steps * 1e3,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "mid-scale: 138000 users x 27000 items, 20M Zipf(1.1) ratings (18M train), "
-                               "k=64, 64x64 blocks, lr 0.005, reg 0.05",
-                   "m": prob.m, "n": prob.n, "n_train": len(tr), "k": cfg.k, "b": cfg.b},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "copy_kernel_GBps": copy_gbps,
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)",
-                     "kernel": "sgd stratum kernel", "algorithmic_bytes_per_launch": abytes / cfg.b,
-                     "avg_launch_ms": per_launch_ms},
-        "cpu_baseline": cpu,
-        "rmse_test": rmse,
-        "parity_1epoch_max_abs": parity,
-        "rmse_match": match,
-        "critical_path_ratings_per_epoch": cp,
-        "sgd_chain": chain,
-        "load_s": load_s,
-        "rmse_pass": rmse_out,
-        "topk": topk,
+        "config": {"workload": "large-scale: 480000 users x 17800 items, 100M Zipf(1.0) integer ratings "
+                               "(90M train), k=128, 128x128 blocks, lr 0.005, reg 0.05",
+                   "m": head["m"], "n": head["n"], "n_train": head["n_train"], "k": head["k"], "b": head["b"]},
+        "roofline": head["roofline"],
+        "cpu_baseline": head["cpu_baseline"],
+        "rmse_test": head["rmse_test"],
+        "parity_1epoch_max_abs": head["parity_1epoch_max_abs"],
+        "rmse_match": head["rmse_match"],
+        "load_s": head["load_s"],
+        "rmse_pass": head["rmse_pass"],
+        "topk_all_users": head["topk_all_users"],
+        "mid": mid,
         "serving": serving_out,
         "batched": batched_out,
         "paper_protocol": paper_out,
         "incremental": incr_out,
         "out_of_core": ooc_out,
-        "large": large_out,
     }
     print(json.dumps(line), flush=True)
 

@@ -41,7 +41,8 @@ MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}  # MI355X dense matrix peaks
 # that makes the same counter read a plain copy kernel's known bytes; valid
 # for the kernel sources with this sha1 and reported as null once they
 # change.
-SGD_TRAFFIC = {}
+SGD_TRAFFIC = {"large": {"sources_sha1": "74d1c743586dfc652929386b49938ffb9f600e93",
+                         "fetch_bytes": 61719.5 * 1024 * 2.0, "write_bytes": 111948.1 * 1024 * 1.0}}
 SGD_SOURCES = ["paper_1907_07410_amd/csrc/sgd.hip", "paper_1907_07410_amd/csrc/plan.hip",
                "paper_1907_07410_amd/csrc/plan.h", "paper_1907_07410_amd/csrc/wave.h"]
 
@@ -647,6 +648,57 @@ def train_leg(binding, args, torch, cfg, steps, warmup, cpu_epochs, copy_gbps):
     return out, G, prob
 
 
+def tuned_grid_leg(binding, args, torch, cfg, prob, with_oracle):
+    """The same workload on the block grid the library's autotuner picks for
+    it (a batch of one problem created without a grid: the cost model of the
+    dependency chain and block staging, fitted from timed epochs), trained
+    for the configuration's epochs through the batch's launches (one per
+    stratum).  Epochs 2 to the last are timed; the test RMSE after the last
+    is compared with the FP64 oracle's on the same grid, the same schedule
+    and the same initial values."""
+    tr, te = prob.train, prob.test
+    bt = binding.Batch([(prob.m, prob.n)], cfg.k, seed=args.seed + 1000)
+    bt.load(0, tr.u, tr.i, tr.r)
+    t0 = time.time()
+    bt.tune()
+    tune_s = time.time() - t0
+    b, waves, predicted = bt.info(0)
+    bt.epochs(1, cfg.lr, cfg.reg)
+    bt.timing(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bt.epochs(cfg.epochs - 1, cfg.lr, cfg.reg)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms, launches = bt.timing(reset=True)
+    G = bt.problem(0)
+    g_te = G.rmse(te.u, te.i, te.r)
+    abytes, _, _ = algorithmic_bytes(tr.u, tr.i, prob.m, prob.n, b, cfg.k)
+    out = {"b": b, "waves": waves, "tune_s": tune_s, "model_ms_per_epoch": predicted,
+           "updates_per_s": len(tr) * (cfg.epochs - 1) / el, "ms_per_epoch": el / (cfg.epochs - 1) * 1e3,
+           "kernel_ms_per_epoch": ms / (cfg.epochs - 1), "launches_per_epoch": launches / (cfg.epochs - 1),
+           "algorithmic_bytes_per_epoch": abytes,
+           "achieved_GBps": abytes / (ms / (cfg.epochs - 1) / 1e3) / 1e9,
+           "gpu_test_rmse": g_te}
+    out["frac_of_hbm_peak"] = out["achieved_GBps"] / HBM_PEAK_GBS
+    if with_oracle:
+        import oracle
+        threads = max(1, min(len(os.sched_getaffinity(0)), 64))
+        O = oracle.Model(prob.m, prob.n, cfg.k, b, seed=args.seed + 1000, order_mode=0)
+        O.load(tr.u, tr.i, tr.r)
+        for _ in range(cfg.epochs):
+            O.epoch(cfg.lr, cfg.reg, threads=threads)
+        o_te = O.rmse(te.u, te.i, te.r)
+        out["rmse_match"] = {"epochs": cfg.epochs, "gpu_test_rmse": g_te, "oracle_test_rmse": o_te,
+                             "abs_diff": abs(g_te - o_te), "matched": bool(abs(g_te - o_te) <= 1e-3)}
+        del O
+    log(f"{cfg.name}: autotuned grid {b}x{b} ({waves} waves, tuned in {tune_s:.1f}s): "
+        f"{out['updates_per_s'] / 1e6:.0f}M updates/s, {out['ms_per_epoch']:.2f} ms/epoch, test rmse {g_te:.6f}"
+        + (f" (oracle {out['rmse_match']['oracle_test_rmse']:.6f})" if with_oracle else ""))
+    bt.close()
+    return out
+
+
 def topk_all_users(binding, torch, G, prob, cfg):
     """Top-100 for every user in FP32 and in BF16 with FP32 rescoring (GPU
     time with events on the library's stream; contraction FLOPs 2 m n k
@@ -819,7 +871,10 @@ def main():
     head, G, prob = train_leg(binding, args, torch, cfg, args.steps, args.warmup, cpu_epochs, copy_gbps)
     head["topk_all_users"] = topk_all_users(binding, torch, G, prob, cfg)
     G.close()
-    del G, prob
+    del G
+    if not args.headline_only:
+        head["tuned_grid"] = tuned_grid_leg(binding, args, torch, cfg, prob, not args.no_cpu_baseline)
+    del prob
     mid = None
     ooc_out = None
     if not args.no_mid:
@@ -830,6 +885,7 @@ def main():
             mid["topk"] = topk_batch(binding, torch, Gm, mprob, mcfg, args.topk_users, 7)
         Gm.close()
         del Gm
+        mid["tuned_grid"] = tuned_grid_leg(binding, args, torch, mcfg, mprob, not args.no_cpu_baseline)
         ooc_out = None if args.no_out_of_core else out_of_core_leg(binding, args, mprob, mcfg)
         del mprob
     serving_out = serving_leg(binding, args) if args.serving_requests > 0 else None
@@ -870,6 +926,7 @@ def main():
         "load_s": head["load_s"],
         "rmse_pass": head["rmse_pass"],
         "topk_all_users": head["topk_all_users"],
+        "tuned_grid": head.get("tuned_grid"),
         "mid": mid,
         "serving": serving_out,
         "batched": batched_out,

@@ -5,11 +5,10 @@
 // The score matrix users x items is the one dense contraction of the
 // method, so it runs on MFMA and is never stored; the work that remains is
 // selection.  Three passes per request:
-//  1. threshold: each user's scores against a fixed sample of s = 1024
-//     evenly spaced item ids give a score that at least r sampled scores
-//     reach (a 256-bin histogram between the sample's extremes), r chosen so
-//     that the chance that fewer than the needed number of items reach it is
-//     below 1e-6 (no threshold when n <= 1024: every item is a candidate);
+//  1. threshold: the r-th best of each user's scores against a fixed sample
+//     of s = 1024 evenly spaced item ids, r chosen so that the chance that
+//     fewer than the needed number of items reach it is below 1e-6 (no
+//     threshold when n <= 1024: every item is a candidate);
 //  2. filter: the full user x item contraction, split over the item range
 //     across workgroups; every score at or above the user's threshold is
 //     appended to the user's candidate buffer in global memory;
@@ -189,10 +188,11 @@ struct ItemFrag {
 };
 
 // Dot products of a 16-item x 16-user tile: acc[r] = score of user
-// (lane % 16) with item (tile item 4 * (lane / 16) + r).
+// (lane % 16) with item (tile item 4 * (lane / 16) + r), accumulated onto
+// the given start (the item biases where the caller wants whole scores).
 template <int KC, bool BF16>
-__device__ __forceinline__ f32x4 tile_mma(const UserFrag<KC, BF16> &U, const ItemFrag<KC, BF16> &A) {
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+__device__ __forceinline__ f32x4 tile_mma(const UserFrag<KC, BF16> &U, const ItemFrag<KC, BF16> &A,
+                                          f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f}) {
     if (!BF16) {
 #pragma unroll
         for (int c = 0; c < KC; ++c) {
@@ -212,33 +212,34 @@ __device__ __forceinline__ f32x4 tile_mma(const UserFrag<KC, BF16> &U, const Ite
 template <int KC, bool BF16>
 __device__ __forceinline__ f32x4 tile_dots(const UserFrag<KC, BF16> &U, const float *__restrict__ Qf,
                                            const uint16_t *__restrict__ Qb, int64_t irow, bool irow_ok, int k,
-                                           int kb, int grp) {
+                                           int kb, int grp, f32x4 start) {
     ItemFrag<KC, BF16> A;
     A.load(Qf, Qb, irow, irow_ok, k, kb, grp);
-    return tile_mma(U, A);
+    return tile_mma(U, A, start);
 }
 
 constexpr int SAMPLE_MAX = 1024;
-constexpr int HBINS = 256;
 
-// Pass 1: threshold per user from its scores over the sample items
-// t * n / s, t < s: a first pass finds the sample's minimum and maximum, a
-// second counts the scores in 256 equal bins between them, and the
-// threshold is the lower edge of the bin below the one holding the r-th best
-// sampled score (so at least r sampled scores reach it, whatever the
-// rounding of the bin index).  Stored as an ordered key; 0 = no threshold
-// (r = 0).  Also clears the user's candidate count.  One workgroup of
-// SMP_WAVES waves per 16-user tile, each wave taking every SMP_WAVES-th
-// sample tile; lane (u, g) of a wave handles user u.
+// Pass 1: threshold per user: the r-th best of its scores over the sample
+// items t * n / s, t < s (so at least r sampled items reach it).  One sweep
+// stores the sampled scores of the tile's 16 users in LDS as ordered keys;
+// then wave w finds user w's r-th largest key bit by bit, from the top: a bit
+// is kept when at least r keys reach the value with it set.  The filter
+// scores a sampled item exactly as this pass does (the same MFMA tile and
+// bias), so the r sampled items at or above the threshold pass it there too.
+// Stored as an ordered key; 0 = no threshold (r = 0).  Also clears the
+// user's candidate count.  One workgroup of SMP_WAVES waves per 16-user tile,
+// each wave taking every SMP_WAVES-th sample tile in the sweep; lane (u, g)
+// holds user u's scores.
 constexpr int SMP_WAVES = 16;
+static_assert(SMP_WAVES == TU, "one wave per user of the tile selects its threshold");
 
 template <int KC, bool BF16>
 __global__ __launch_bounds__(SMP_WAVES *WAVE) void sample_threshold_kernel(
     const float *__restrict__ Ug, const uint16_t *__restrict__ Ugb, const float *__restrict__ Qf,
     const uint16_t *__restrict__ Qb, const float *__restrict__ bi, int64_t n, int k, int kp, int kb, int s, int r,
     uint32_t *__restrict__ thr, uint32_t *__restrict__ cnt) {
-    __shared__ uint32_t hist[TU][HBINS];
-    __shared__ float ext[SMP_WAVES][2][TU];
+    __shared__ uint32_t keys[TU][SAMPLE_MAX];
     const int tid = threadIdx.x, lane = tid % WAVE, wave = tid / WAVE;
     const int64_t tile = blockIdx.x;
     const int ucol = lane % 16, grp = lane / 16;
@@ -247,13 +248,9 @@ __global__ __launch_bounds__(SMP_WAVES *WAVE) void sample_threshold_kernel(
         if (tid < TU) thr[tile * TU + tid] = 0u;
         return;
     }
-    for (int x = tid; x < TU * HBINS; x += SMP_WAVES * WAVE) (&hist[0][0])[x] = 0u;
     UserFrag<KC, BF16> U;
     U.load(Ug, Ugb, tile * TU + ucol, kp, kb, grp);
     const int step = SMP_WAVES * TI;
-    // scores of this wave's sample tiles, with the next tile's rows loaded
-    // while the current one is multiplied; f(t, v) is called for every
-    // sample index t < s of the tile and its score v
     auto sample_bias = [&](int t0, float (&b)[4]) {
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
@@ -261,80 +258,63 @@ __global__ __launch_bounds__(SMP_WAVES *WAVE) void sample_threshold_kernel(
             b[rr] = t < s ? bi[(int64_t)t * n / s] : 0.f;
         }
     };
-    auto sweep = [&](auto &&f) {
+    // the wave's sample tiles, the next tile's rows loaded while the current
+    // one is multiplied
+    {
         ItemFrag<KC, BF16> A, An;
         float b[4], bn[4];
         int t0 = wave * TI;
-        {
-            const int ta = t0 + ucol;
-            A.load(Qf, Qb, (int64_t)ta * n / s, ta < s, k, kb, grp);
-            sample_bias(t0, b);
-        }
+        const int ta = t0 + ucol;
+        A.load(Qf, Qb, (int64_t)ta * n / s, ta < s, k, kb, grp);
+        sample_bias(t0, b);
         for (; t0 < s; t0 += step) {
             const int tn = t0 + step + ucol;
             An.load(Qf, Qb, (int64_t)tn * n / s, tn < s, k, kb, grp);
             sample_bias(t0 + step, bn);
-            const f32x4 acc = tile_mma(U, A);
+            // the bias as the accumulator's start, as in the filter
+            const f32x4 acc = tile_mma(U, A, f32x4{b[0], b[1], b[2], b[3]});
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
                 const int t = t0 + 4 * grp + rr;
-                if (t < s) f(t, acc[rr] + b[rr]);
+                if (t < s) keys[ucol][t] = float_to_ordered(acc[rr]);
             }
             A = An;
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) b[rr] = bn[rr];
         }
-    };
-    float vmin = INFINITY, vmax = -INFINITY;
-    sweep([&](int, float v) {
-        vmin = fminf(vmin, v);
-        vmax = fmaxf(vmax, v);
-    });
-    // the four lanes of a user (ucol + 16 g), then the waves
-    vmin = fminf(vmin, __shfl_xor(vmin, 16, WAVE));
-    vmax = fmaxf(vmax, __shfl_xor(vmax, 16, WAVE));
-    vmin = fminf(vmin, __shfl_xor(vmin, 32, WAVE));
-    vmax = fmaxf(vmax, __shfl_xor(vmax, 32, WAVE));
-    if (lane < TU) {
-        ext[wave][0][lane] = vmin;
-        ext[wave][1][lane] = vmax;
     }
     __syncthreads();
-    vmin = ext[0][0][ucol];
-    vmax = ext[0][1][ucol];
+    // wave w: user w's r-th largest key
+    const uint32_t *mine = keys[wave];
+    constexpr int PER = SAMPLE_MAX / WAVE;
+    uint32_t kv[PER];
 #pragma unroll
-    for (int w = 1; w < SMP_WAVES; ++w) {
-        vmin = fminf(vmin, ext[w][0][ucol]);
-        vmax = fmaxf(vmax, ext[w][1][ucol]);
+    for (int j = 0; j < PER; ++j) {
+        const int t = lane + WAVE * j;
+        kv[j] = t < s ? mine[t] : 0u;  // 0: below every real key, never counted
     }
-    const float width = vmax - vmin;
-    const float scale = width > 0.f ? (float)HBINS / width : 0.f;
-    sweep([&](int, float v) {
-        const int bin = min(HBINS - 1, max(0, (int)((v - vmin) * scale)));
-        atomicAdd(&hist[ucol][bin], 1u);
-    });
-    __syncthreads();
-    if (tid < TU) {
-        // highest bin b with at least r scores in bins b and above
-        int acc = 0, b = HBINS - 1;
-        for (; b > 0; --b) {
-            acc += (int)hist[tid][b];
-            if (acc >= r) break;
-        }
-        const float edge = vmin + (float)(b - 1) / scale;
-        thr[tile * TU + tid] = b <= 1 ? float_to_ordered(vmin) : float_to_ordered(fminf(edge, vmax));
+    uint32_t ans = 0u;
+    for (int bit = 31; bit >= 0; --bit) {
+        const uint32_t cand = ans | (1u << bit);
+        int c = 0;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) c += __popcll(__ballot(kv[j] >= cand));
+        if (c >= r) ans = cand;
     }
+    if (lane == 0) thr[tile * TU + wave] = ans;
 }
 
 // Pass 2: every score at or above its user's threshold goes to the user's
-// candidate buffer (capg keys; the count keeps growing past capg so that
-// an overflow is seen).  Grid: groups of UT user tiles x item splits; a
-// wave holds the user fragments of its UT tiles, so each item tile it loads
-// feeds UT tile products (UT times fewer item-table reads than one tile per
-// wave).  Tiles at or beyond `tiles` are skipped.  Candidates gather in LDS
-// (FLT_LDS per user, positions from LDS atomics) and go to the global
-// buffer at the end with one counter reservation per user; a user that
-// fills its LDS space sends the rest through the global counter one by one.
+// candidate buffer (capg keys; the count keeps growing past capg so that an
+// overflow is seen).  Grid: groups of UT user tiles x item splits; a wave
+// holds the user fragments of its UT tiles, so each item tile it loads feeds
+// UT tile products (UT times fewer item-table reads than one tile per wave).
+// Tiles at or beyond `tiles` are skipped.  Candidates gather in LDS (FLT_LDS
+// per user, positions from LDS atomics).  A tile adds at most 16 to a user's
+// list, so when some list holds more than FLT_LDS - 16 after a tile, the
+// wave moves every non-empty list to the global buffer (one counter
+// reservation per user, all users' reservations issued together); the rest
+// goes there at the end.
 constexpr int FLT_LDS = 32;
 
 template <int KC, bool BF16, int UT>
@@ -356,86 +336,84 @@ __global__ __launch_bounds__(64) void filter_kernel(const float *__restrict__ Ug
     UserFrag<KC, BF16> U[UT];
     // thresholds as floats: sv >= tf passes every score whose ordered key
     // reaches the threshold (and, at most, a -0 against a +0 threshold too);
-    // no threshold (0) passes everything
+    // no threshold (0) passes every number, and a NaN (an item beyond the
+    // range) nothing
     float tf[UT];
-    bool all[UT];
 #pragma unroll
     for (int q = 0; q < UT; ++q) {
         const int64_t urow = (tile0 + (q < nt ? q : 0)) * TU + ucol;
         U[q].load(Ug, Ugb, urow, kp, kb, grp);
         const uint32_t t = thr[urow];
-        all[q] = t == 0u;
         tf[q] = t == 0u ? -INFINITY : ordered_to_float(t);
     }
     __syncthreads();
-    // item biases of this lane's four score items of a tile
-    auto load_bias = [&](int64_t ib, float (&b)[4]) {
+    // item biases of this lane's four score items of a tile (items
+    // 4 grp .. 4 grp + 3, 16-byte aligned): one load on a whole tile, NaN
+    // beyond the range
+    auto load_bias = [&](int64_t ib, f32x4 &b) {
+        const int64_t item = ib + 4 * grp;
+        if (ib + TI <= iend) {
+            b = *reinterpret_cast<const f32x4 *>(bi + item);
+        } else {
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int64_t item = ib + 4 * grp + rr;
-            b[rr] = item < iend ? bi[item] : 0.f;
+            for (int rr = 0; rr < 4; ++rr) b[rr] = item + rr < iend ? bi[item + rr] : __builtin_nanf("");
         }
     };
+    // lists to the global buffer: lane x reserves room for user x's list
+    // (one returning atomic per user, all in flight together), then the lanes
+    // copy each list (at most FLT_LDS keys) and empty it.  One wave per
+    // workgroup: its LDS accesses happen in program order.
+    static_assert(UT * TU <= WAVE && FLT_LDS <= WAVE, "one lane per user and per list entry");
+    auto flush = [&]() {
+        const bool own = lane < nt * TU;
+        const uint32_t c = own ? lcnt[lane] : 0u;
+        uint32_t g = 0u;
+        if (c) g = atomicAdd(&cnt[(tile0 * TU + lane)], c);
+        uint64_t users = __ballot(c != 0u);
+        while (users) {
+            const int x = __builtin_ctzll(users);
+            users &= users - 1;
+            const uint32_t cx = __shfl(c, x), gx = __shfl(g, x);
+            const int64_t urow = tile0 * TU + x;
+            if ((uint32_t)lane < cx && gx + lane < (uint32_t)capg) cand[urow * capg + gx + lane] = lbuf[x][lane];
+        }
+        if (c) lcnt[lane] = 0u;
+    };
     ItemFrag<KC, BF16> A, An;
-    float b[4], bn[4];
+    f32x4 b, bn;
     A.load(Qf, Qb, ibeg + ucol, ibeg + ucol < iend, k, kb, grp);
     load_bias(ibeg, b);
+    bn = b;
     for (int64_t ib = ibeg; ib < iend; ib += TI) {
         // the next tile's rows and biases, loaded while this one is multiplied
         const int64_t inext = ib + TI + ucol;
         An.load(Qf, Qb, inext, inext < iend, k, kb, grp);
-        load_bias(ib + TI, bn);
+        if (ib + TI < iend) load_bias(ib + TI, bn);
+        // scores with the item bias as the accumulator's start
         f32x4 acc[UT];
 #pragma unroll
-        for (int q = 0; q < UT; ++q) acc[q] = tile_mma(U[q], A);
+        for (int q = 0; q < UT; ++q) acc[q] = tile_mma(U[q], A, b);
         A = An;
-        // this lane's scores at or above the threshold, per user tile
-        uint32_t pass[UT], base[UT];
 #pragma unroll
         for (int q = 0; q < UT; ++q) {
-            pass[q] = 0u;
+            if (q >= nt) continue;
+            uint32_t pass = 0u;
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const float sv = acc[q][rr] + b[rr];
-                const bool ok = q < nt && ib + 4 * grp + rr < iend && (all[q] || sv >= tf[q]);
-                pass[q] |= ok ? 1u << rr : 0u;
-            }
-        }
+            for (int rr = 0; rr < 4; ++rr) pass |= acc[q][rr] >= tf[q] ? 1u << rr : 0u;
+            if (pass) {
+                const uint32_t base = atomicAdd(&lcnt[q * TU + ucol], (uint32_t)__popc(pass));
 #pragma unroll
-        for (int q = 0; q < UT; ++q)
-            base[q] = pass[q] ? atomicAdd(&lcnt[q * TU + ucol], (uint32_t)__popc(pass[q])) : 0u;
-#pragma unroll
-        for (int q = 0; q < UT; ++q) {
-            if (!pass[q]) continue;
-            uint32_t pos = base[q];
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                if (pass[q] >> rr & 1u) {
-                    const uint64_t key = rank_key(acc[q][rr] + b[rr], (int32_t)(ib + 4 * grp + rr));
-                    if (pos < (uint32_t)FLT_LDS) {
-                        lbuf[q * TU + ucol][pos] = key;
-                    } else {
-                        const int64_t urow = (tile0 + q) * TU + ucol;
-                        const uint32_t g = atomicAdd(&cnt[urow], 1u);
-                        if (g < (uint32_t)capg) cand[urow * capg + g] = key;
-                    }
-                    ++pos;
+                for (int rr = 0; rr < 4; ++rr) {
+                    const uint32_t pos = base + (uint32_t)__popc(pass & ((1u << rr) - 1u));
+                    if ((pass >> rr & 1u) && pos < (uint32_t)FLT_LDS)
+                        lbuf[q * TU + ucol][pos] = rank_key(acc[q][rr], (int32_t)(ib + 4 * grp + rr));
                 }
             }
         }
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) b[rr] = bn[rr];
+        b = bn;
+        if (__ballot(lane < nt * TU && lcnt[lane] > (uint32_t)(FLT_LDS - 16))) flush();
     }
-    __syncthreads();
-    // flush: lane x owns user x of the group
-    for (int x = lane; x < nt * TU; x += WAVE) {
-        const uint32_t c = std::min<uint32_t>(lcnt[x], FLT_LDS);
-        if (c == 0u) continue;
-        const int64_t urow = tile0 * TU + x;
-        const uint32_t g = atomicAdd(&cnt[urow], c);
-        for (uint32_t j = 0; j < c; ++j)
-            if (g + j < (uint32_t)capg) cand[urow * capg + g + j] = lbuf[x][j];
-    }
+    flush();
 }
 
 // User tiles per filter wave, as measured: two at k <= 64, four at
@@ -598,13 +576,17 @@ __global__ __launch_bounds__(64) void score_select_kernel(const float *__restric
 
     for (int64_t ib = 0; ib < n; ib += TI) {
         const int64_t irow = ib + ucol;
-        const f32x4 acc = tile_dots<KC, BF16>(U, Qf, Qb, irow, irow < n, k, kb, grp);
+        f32x4 bias;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) bias[r] = ib + 4 * grp + r < n ? bi[ib + 4 * grp + r] : 0.f;
+        // the scores as the filter forms them (the bias as the start)
+        const f32x4 acc = tile_dots<KC, BF16>(U, Qf, Qb, irow, irow < n, k, kb, grp, bias);
         // lane holds items ib + 4*grp + r for user ucol
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const int64_t item = ib + 4 * grp + r;
             if (item < n) {
-                const float s = acc[r] + bi[item];
+                const float s = acc[r];
                 if (s > thr) {
                     const int pos = atomicAdd(&sh.cnt[ucol], 1);
                     sh.cand[ucol][pos] = rank_key(s, (int32_t)item);

@@ -90,9 +90,10 @@ typedef enum {
     /* 1: the next load keeps the ratings in pinned host memory (out of core,
      * Section 6's unbounded block count): partition and step plans are made
      * on the host, each stratum's work is laid out contiguously, and an epoch
-     * copies stratum after stratum into a ring of three device buffers on a
-     * copy stream while earlier strata run.  Device memory then holds the
-     * factor tables and three strata.  The kernels, and so the results, are
+     * copies groups of strata (up to 8, at most 64 MiB when a stratum is
+     * smaller, else one) in the epoch's order into a ring of three device
+     * buffers on a copy stream while earlier groups run.  Device memory then
+     * holds the factor tables and three such groups.  The kernels, and so the results, are
      * those of a resident load with the same SGD kernel; mu is summed on the
      * host in input order.  Such a load takes host arrays only
      * (bmf_load_ratings), fixes the SGD kernel (set BMF_OPT_SGD_KERNEL before

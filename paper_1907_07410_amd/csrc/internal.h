@@ -125,10 +125,15 @@ struct Plan {
 // table (b + 1 unit offsets, by position); OOC_BUFS device buffers take
 // turns receiving strata on the copy stream while earlier ones run.
 constexpr int OOC_BUFS = 3;
+// Strata per ring buffer: at most OOC_GROUP, and as many as fit in
+// OOC_SLOT_BYTES (at least one).
+constexpr int OOC_GROUP = 8;
+constexpr size_t OOC_SLOT_BYTES = size_t(64) << 20;
 struct OutOfCore {
     bool on = false;
     int variant = 1;        // 1: records for the reference kernels, 2: planned steps
     size_t unit = 0;        // bytes per unit (one record, or one step of PLAN_W slot records)
+    int group = 1;          // strata per ring buffer (one copy, one wait each way per group)
     std::vector<int64_t> s_off;    // b + 1 byte offsets of the strata in `data`
     std::vector<int64_t> s_units;  // units of each stratum (its table follows them)
     PinnedBuf data;                // stratum-major units and tables

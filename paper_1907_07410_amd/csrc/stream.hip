@@ -159,10 +159,16 @@ void ooc_load(Model &M, const int32_t *u, const int32_t *i, const float *r, int6
             units += bptr[blk + 1] - bptr[blk];
         }
         X.s_units[s] = units;
-        const size_t bytes = (size_t)units * unit + tbytes;
+        // strata start 256-byte aligned, so that consecutive ones can be
+        // copied into one ring buffer with a single copy
+        const size_t bytes = ((size_t)units * unit + tbytes + 255) & ~size_t(255);
         X.s_off[s + 1] = X.s_off[s] + (int64_t)bytes;
         max_bytes = std::max(max_bytes, bytes);
     }
+    // strata per ring buffer: up to OOC_GROUP of them in OOC_SLOT_BYTES, so
+    // that an epoch has b / group copy-to-kernel and kernel-to-copy waits
+    // between the streams instead of b of each
+    X.group = (int)std::max<size_t>(1, std::min<size_t>(std::min(OOC_GROUP, b), OOC_SLOT_BYTES / std::max<size_t>(1, max_bytes)));
     X.data.alloc((size_t)X.s_off[b]);
     for (int s = 0; s < b; ++s) {
         unsigned char *base = X.data.as<unsigned char>() + X.s_off[s];
@@ -187,7 +193,7 @@ void ooc_load(Model &M, const int32_t *u, const int32_t *i, const float *r, int6
     }
     X.perm.swap(perm);
     for (int q = 0; q < OOC_BUFS; ++q) {
-        X.stage[q].alloc(max_bytes);
+        X.stage[q].alloc(max_bytes * X.group);
         BMF_HIP(hipEventCreateWithFlags(&X.copied[q], hipEventDisableTiming));
         BMF_HIP(hipEventCreateWithFlags(&X.used[q], hipEventDisableTiming));
     }
@@ -199,6 +205,7 @@ void ooc_load(Model &M, const int32_t *u, const int32_t *i, const float *r, int6
     std::swap(M.ooc.on, X.on);
     std::swap(M.ooc.variant, X.variant);
     std::swap(M.ooc.unit, X.unit);
+    std::swap(M.ooc.group, X.group);
     M.ooc.s_off.swap(X.s_off);
     M.ooc.s_units.swap(X.s_units);
     M.ooc.data.swap(X.data);
@@ -236,18 +243,34 @@ void ooc_load(Model &M, const int32_t *u, const int32_t *i, const float *r, int6
 void ooc_epoch(Model &M, const int32_t *order, const HP &hp, int variant) {
     OutOfCore &X = M.ooc;
     const int b = M.b;
-    for (int pos = 0; pos < b; ++pos) {
-        const int s = order[pos], q = pos % OOC_BUFS;
-        // the buffer is free once the kernel that last read it has finished
+    for (int g0 = 0, gi = 0; g0 < b; g0 += X.group, ++gi) {
+        const int g1 = std::min(b, g0 + X.group), q = gi % OOC_BUFS;
+        // the buffer is free once the kernels that last read it have finished
         if (X.used_valid[q]) BMF_HIP(hipStreamWaitEvent(X.copy, X.used[q], 0));
-        // one copy: the stratum's units and its block table behind them
-        BMF_HIP(hipMemcpyAsync(X.stage[q].p, X.data.as<unsigned char>() + X.s_off[s],
-                               (size_t)(X.s_off[s + 1] - X.s_off[s]), hipMemcpyHostToDevice, X.copy));
+        // the group's strata back to back (each its units and its block table
+        // behind them), one copy per run of strata adjacent in host memory
+        unsigned char *dst = X.stage[q].as<unsigned char>();
+        std::vector<size_t> at(g1 - g0);
+        size_t off = 0;
+        for (int pos = g0; pos < g1;) {
+            int end = pos + 1;
+            while (end < g1 && order[end] == order[end - 1] + 1) ++end;
+            const int s0 = order[pos], s1 = order[end - 1];
+            const size_t len = (size_t)(X.s_off[s1 + 1] - X.s_off[s0]);
+            BMF_HIP(hipMemcpyAsync(dst + off, X.data.as<unsigned char>() + X.s_off[s0], len, hipMemcpyHostToDevice,
+                                   X.copy));
+            for (int x = pos; x < end; ++x) at[x - g0] = off + (size_t)(X.s_off[order[x]] - X.s_off[s0]);
+            off += len;
+            pos = end;
+        }
         BMF_HIP(hipEventRecord(X.copied[q], X.copy));
         BMF_HIP(hipStreamWaitEvent(M.stream, X.copied[q], 0));
-        const unsigned char *st = X.stage[q].as<unsigned char>();
-        launch_stratum(M, s, hp, variant,
-                       StratumData{st, reinterpret_cast<const int64_t *>(st + (size_t)X.s_units[s] * X.unit), 0});
+        for (int pos = g0; pos < g1; ++pos) {
+            const int s = order[pos];
+            const unsigned char *st = dst + at[pos - g0];
+            launch_stratum(M, s, hp, variant,
+                           StratumData{st, reinterpret_cast<const int64_t *>(st + (size_t)X.s_units[s] * X.unit), 0});
+        }
         BMF_HIP(hipEventRecord(X.used[q], M.stream));
         X.used_valid[q] = true;
     }

@@ -45,13 +45,18 @@ def test_host_partition_matches_oracle(orc, m, n, b, dup):
     assert np.array_equal(bp, obp) and np.array_equal(perm, operm)
 
 
-@pytest.mark.parametrize("k,b,kernel", [(64, 8, None), (64, 8, 1), (13, 128, None), (32, 4, 2), (200, 4, None)])
-def test_bit_identical_to_resident(k, b, kernel):
+@pytest.mark.parametrize("order_mode", [0, 1])
+@pytest.mark.parametrize("k,b,kernel", [(64, 8, None), (64, 8, 1), (13, 128, None), (32, 4, 2), (200, 4, None),
+                                        (32, 12, None), (16, 20, 1)])
+def test_bit_identical_to_resident(k, b, kernel, order_mode):
+    """Strata travel in groups of up to eight per ring buffer: in the epoch's
+    order, so with the identity order a group is one copy and with the seeded
+    order several; grids of 12 and 20 end on a partial group."""
     from paper_1907_07410_amd import binding as B
     d = data()
     out = []
     for ooc in (False, True):
-        G = model(B, 1500, 700, k, b, ooc, kernel=kernel, mu_mode=1)
+        G = model(B, 1500, 700, k, b, ooc, kernel=kernel, mu_mode=1, order_mode=order_mode)
         G.load_ratings(d.u, d.i, d.r)
         for _ in range(3):
             G.epoch_hp(HP)

@@ -290,6 +290,9 @@ struct TopkPlan {
     int64_t nu = 0, nu_pad = 0;
     int K = 0, Ksel = 0, kp = 0, kb = 0;
     bool bf = false;
+    // BF16: drop candidates that provably cannot reach the FP32 top K before
+    // rescoring (on unless BMF_TOPK_PRUNE=0 is in the environment)
+    int prune = 1;
     // threshold sample: s items, threshold = the r-th best sampled score
     // (r = 0: no threshold); candidate buffers of capg keys per user;
     // the filter splits the item range into S pieces of per_split items

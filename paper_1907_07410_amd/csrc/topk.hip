@@ -31,6 +31,7 @@
 // the batch.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <mutex>
 
 #include "internal.h"
@@ -66,6 +67,33 @@ __global__ void bf16_table_kernel(const float *__restrict__ A, int64_t rows, int
 // Gather the requested users' rows: FP32 (stride kp, zero padded), BF16
 // (stride kb) and the per-user offset mu + bu_u.  Invalid ids get a zero
 // vector and a NaN offset (their rows decode to item -1).
+// Bounds used by the BF16 path's candidate drop: st[0] >= max_j ||Q_j||_2
+// (the FP32 norm inflated by 1e-4 relative, more than its rounding for
+// k <= 256) and st[1] = max_j |bi_j|, as non-negative floats whose bits
+// order like the values.
+__global__ void item_stats_clear_kernel(float *st) {
+    if (threadIdx.x < 2) st[threadIdx.x] = 0.f;
+}
+__global__ void item_stats_kernel(const float *__restrict__ Q, const float *__restrict__ bi, int64_t n, int k,
+                                  float *st) {
+    float qn = 0.f, bm = 0.f;
+    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+        float s2 = 0.f;
+        for (int f = 0; f < k; ++f) s2 = fmaf(Q[j * k + f], Q[j * k + f], s2);
+        qn = fmaxf(qn, sqrtf(s2) * 1.0001f);
+        bm = fmaxf(bm, fabsf(bi[j]));
+    }
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        qn = fmaxf(qn, __shfl_xor(qn, off, WAVE));
+        bm = fmaxf(bm, __shfl_xor(bm, off, WAVE));
+    }
+    if (__lane_id() == 0) {
+        atomicMax(reinterpret_cast<unsigned int *>(st), __float_as_uint(qn));
+        atomicMax(reinterpret_cast<unsigned int *>(st) + 1, __float_as_uint(bm));
+    }
+}
+
 __global__ void gather_users_kernel(const int32_t *__restrict__ users, int64_t nu, int64_t nu_pad, int64_t m,
                                     const float *__restrict__ P, const float *__restrict__ bu, float mu, int k,
                                     int kp, int kb, float *__restrict__ Ug, uint16_t *__restrict__ Ugb,
@@ -306,11 +334,12 @@ __global__ __launch_bounds__(SMP_WAVES *WAVE) void sample_threshold_kernel(
 
 // Pass 2: every score at or above its user's threshold goes to the user's
 // candidate buffer (capg keys; the count keeps growing past capg so that an
-// overflow is seen).  Grid: groups of UT user tiles x item splits; a wave
-// holds the user fragments of its UT tiles, so each item tile it loads feeds
-// UT tile products (UT times fewer item-table reads than one tile per wave).
-// Tiles at or beyond `tiles` are skipped.  Candidates gather in LDS (FLT_LDS
-// per user, positions from LDS atomics).  A tile adds at most 16 to a user's
+// overflow is seen).  Grid: groups of UT user tiles x item splits (the split
+// varying fastest); a wave holds the user fragments of its UT tiles, so each
+// item tile it loads feeds UT tile products (UT times fewer item-table reads
+// than one tile per wave).  Tiles at or beyond `tiles` are skipped.
+// Candidates gather in LDS (FLT_LDS per user, each the score and the item's
+// offset in the split, positions from LDS atomics).  A tile adds at most 16 to a user's
 // list, so when some list holds more than FLT_LDS - 16 after a tile, the
 // wave moves every non-empty list to the global buffer (one counter
 // reservation per user, all users' reservations issued together); the rest
@@ -318,17 +347,22 @@ __global__ __launch_bounds__(SMP_WAVES *WAVE) void sample_threshold_kernel(
 constexpr int FLT_LDS = 32;
 
 template <int KC, bool BF16, int UT>
-__global__ __launch_bounds__(64) void filter_kernel(const float *__restrict__ Ug, const uint16_t *__restrict__ Ugb,
+__global__ __launch_bounds__(64, 2) void filter_kernel(const float *__restrict__ Ug, const uint16_t *__restrict__ Ugb,
                                                     const float *__restrict__ Qf, const uint16_t *__restrict__ Qb,
                                                     const float *__restrict__ bi, int64_t n, int k, int kp, int kb,
-                                                    int64_t tiles, int64_t per_split,
+                                                    int64_t tiles, int64_t per_split, int splits,
                                                     const uint32_t *__restrict__ thr, uint32_t *__restrict__ cnt,
                                                     int capg, uint64_t *__restrict__ cand) {
-    __shared__ uint64_t lbuf[UT * TU][FLT_LDS];
+    // a list entry: the score and the item's offset in the split (6 bytes)
+    __shared__ float lsc[UT * TU][FLT_LDS];
+    __shared__ uint16_t lit[UT * TU][FLT_LDS];
     __shared__ uint32_t lcnt[UT * TU];
     const int lane = threadIdx.x;
-    const int64_t tile0 = (int64_t)blockIdx.x * UT;
-    const int64_t ibeg = (int64_t)blockIdx.y * per_split;
+    // the item split varies fastest with the workgroup id: workgroups are
+    // dealt to the XCDs in turn, so with a multiple of 8 splits each XCD's L2
+    // holds the item rows of its own splits only
+    const int64_t tile0 = (int64_t)(blockIdx.x / splits) * UT;
+    const int64_t ibeg = (int64_t)(blockIdx.x % splits) * per_split;
     const int64_t iend = std::min<int64_t>(n, ibeg + per_split);
     const int ucol = lane % 16, grp = lane / 16;
     const int nt = (int)std::min<int64_t>(UT, tiles - tile0);  // wave-uniform
@@ -375,7 +409,8 @@ __global__ __launch_bounds__(64) void filter_kernel(const float *__restrict__ Ug
             users &= users - 1;
             const uint32_t cx = __shfl(c, x), gx = __shfl(g, x);
             const int64_t urow = tile0 * TU + x;
-            if ((uint32_t)lane < cx && gx + lane < (uint32_t)capg) cand[urow * capg + gx + lane] = lbuf[x][lane];
+            if ((uint32_t)lane < cx && gx + lane < (uint32_t)capg)
+                cand[urow * capg + gx + lane] = rank_key(lsc[x][lane], (int32_t)(ibeg + lit[x][lane]));
         }
         if (c) lcnt[lane] = 0u;
     };
@@ -405,8 +440,10 @@ __global__ __launch_bounds__(64) void filter_kernel(const float *__restrict__ Ug
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
                     const uint32_t pos = base + (uint32_t)__popc(pass & ((1u << rr) - 1u));
-                    if ((pass >> rr & 1u) && pos < (uint32_t)FLT_LDS)
-                        lbuf[q * TU + ucol][pos] = rank_key(acc[q][rr], (int32_t)(ib + 4 * grp + rr));
+                    if ((pass >> rr & 1u) && pos < (uint32_t)FLT_LDS) {
+                        lsc[q * TU + ucol][pos] = acc[q][rr];
+                        lit[q * TU + ucol][pos] = (uint16_t)(ib - ibeg + 4 * grp + rr);
+                    }
                 }
             }
         }
@@ -425,130 +462,146 @@ static constexpr int filter_tiles_per_wave(int kc, bool bf16) {
 // The latent chunk count the pass kernels are instantiated for.
 static int dispatch_kc(int kc) { return kc <= 2 ? kc : kc <= 4 ? 4 : kc <= 8 ? 8 : 16; }
 
-// Pass 3: one workgroup per user keeps the candidates that can be among its
-// best `need` (a 256-bin histogram of their scores between the smallest and
-// the largest gives a cut bin; every key in the cut bin and above is kept),
+// Pass 3: one wave per user keeps the candidates that can be among its best
+// `need` (a 256-bin histogram of their scores between the smallest and the
+// largest gives a cut bin; every key in the cut bin and above is kept),
 // sorts those (descending keys) and writes the best `need` (0 = none).  A
-// user with fewer than `need` candidates under a real threshold, or with an
-// overflowed buffer, is marked in fail[] for the full-selection kernel.
-constexpr int FIN_WG = 256;
+// user with fewer than `need` candidates under a real threshold, with an
+// overflowed buffer, or keeping more than KEEP keys (scores crowded into one
+// bin) is marked in fail[] for the full-selection kernel.  The wave
+// reads its candidates from the global buffer once per phase (the reads
+// after the first hit in the caches) and needs no workgroup barrier.
+constexpr int FIN_WG = WAVE;
 constexpr int CAPG_MAX = 4096;
-
 constexpr int FIN_BINS = 256;
+constexpr int FIN_KEEP = 1024;  // >= the largest `need` (1008)
+// LDS for the kept keys: 512 when need <= FIN_KEEP_SMALL_NEED (room for the
+// cut bin's extra keys), else FIN_KEEP
+constexpr int FIN_KEEP_SMALL = 512, FIN_KEEP_SMALL_NEED = 384;
+static_assert(FIN_BINS == 4 * WAVE, "four bins per lane");
 
-template <int CAP>
+// Orders this wave's LDS accesses before and after the call (LDS operations
+// of one wave are performed in issue order; this keeps the compiler from
+// moving them across).
+__device__ __forceinline__ void wave_lds_fence() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, WAVE));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, WAVE));
+    return v;
+}
+
+// The histogram cut of one user's candidates by one wave: every key that
+// can be among the best `need` goes to buf (the first KEEP of them; the
+// return value is the kept count, which may exceed KEEP).  edge_rank gets a
+// lower bound on the high half of the key of rank `rank` (<= need): the
+// smallest high half of the bins that hold the best `rank` keys (0 when
+// total <= need and no histogram was made).
+template <int KEEP>
+__device__ __forceinline__ int fin_cut(const uint64_t *__restrict__ mine, int total, int need, int rank,
+                                       uint64_t *buf, uint32_t *hist, uint32_t &edge_rank) {
+    const int lane = threadIdx.x;
+    edge_rank = 0u;
+    if (total <= need) {
+        for (int x = lane; x < total; x += WAVE) buf[x] = mine[x];
+        return total;
+    }
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    for (int x = lane; x < total; x += WAVE) {
+        const uint32_t h = (uint32_t)(mine[x] >> 32);
+        lo = min(lo, h);
+        hi = max(hi, h);
+    }
+    lo = wave_min_u32(lo);
+    hi = wave_max_u32(hi);
+    // histogram of the score halves over [lo, hi] in 256 equal bins; the cut
+    // bin is the highest one with at least `need` keys in it and above, so
+    // every key of the best `need` is in a kept bin
+    const uint64_t span = (uint64_t)(hi - lo) + 1u;
+    auto bin_of = [&](uint64_t key) { return (int)(((uint64_t)((uint32_t)(key >> 32) - lo) * FIN_BINS) / span); };
+#pragma unroll
+    for (int e = 0; e < 4; ++e) hist[4 * lane + e] = 0u;
+    wave_lds_fence();
+    for (int x = lane; x < total; x += WAVE) atomicAdd(&hist[bin_of(mine[x])], 1u);
+    wave_lds_fence();
+    uint32_t h[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) h[e] = hist[4 * lane + e];
+    // suffix sums from the top bin down: lanes above this one first
+    const uint32_t own = h[0] + h[1] + h[2] + h[3];
+    uint32_t above = own;  // inclusive suffix over lanes >= this one
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const uint32_t o = (uint32_t)__shfl_down((int)above, d, WAVE);
+        if (lane + d < WAVE) above += o;
+    }
+    uint32_t suf = above - own;  // keys in the bins above this lane's four
+    // this lane's bins whose suffix reaches need, resp. rank (the suffix only
+    // falls with the bin, so bins 0 .. cut are the ones that do)
+    uint32_t nb = 0u;
+#pragma unroll
+    for (int e = 3; e >= 0; --e) {
+        suf += h[e];
+        nb += (suf >= (uint32_t)need ? 1u : 0u) + (suf >= (uint32_t)rank ? 1u << 16 : 0u);
+    }
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) nb += (uint32_t)__shfl_xor((int)nb, off, WAVE);
+    const int cut = (int)(nb & 0xFFFFu) - 1, cut_rank = (int)(nb >> 16) - 1;
+    // a key is in bin cut_rank or above when its high half reaches
+    // lo + ceil(cut_rank * span / 256)
+    edge_rank = lo + (uint32_t)(((uint64_t)cut_rank * span + FIN_BINS - 1) / FIN_BINS);
+    // compaction: every key of the cut bin and above, in candidate order
+    int m = 0;
+    for (int x0 = 0; x0 < total; x0 += WAVE) {
+        const int x = x0 + lane;
+        uint64_t key = 0ull;
+        bool keep = false;
+        if (x < total) {
+            key = mine[x];
+            keep = bin_of(key) >= cut;
+        }
+        const uint64_t bal = __ballot(keep);
+        const int at = m + __popcll(bal & ((1ull << lane) - 1ull));
+        if (keep && at < KEEP) buf[at] = key;
+        m += __popcll(bal);
+    }
+    return m;
+}
+
+template <int KEEP>
 __global__ __launch_bounds__(FIN_WG) void finish_kernel(const uint32_t *__restrict__ thr,
                                                         const uint32_t *__restrict__ cnt,
                                                         const uint64_t *__restrict__ cand, int capg, int need,
                                                         uint32_t *__restrict__ fail, uint64_t *__restrict__ sel) {
-    static_assert(CAP % FIN_WG == 0 && FIN_BINS == FIN_WG, "one bin per thread");
-    constexpr int PER = CAP / FIN_WG;
-    __shared__ uint64_t buf[CAP];
+    __shared__ uint64_t buf[KEEP];
     __shared__ uint32_t hist[FIN_BINS];
-    __shared__ uint32_t range[2];
-    __shared__ uint32_t wsum[FIN_WG / WAVE];
-    __shared__ int kept;
-    const int tid = threadIdx.x;
+    const int lane = threadIdx.x;
     const int64_t row = blockIdx.x;
     const uint32_t c = cnt[row];
     const bool ok = c <= (uint32_t)capg && (c >= (uint32_t)need || thr[row] == 0u);
-    if (tid == 0) fail[row] = ok ? 0u : 1u;
-    if (!ok) return;
-    const int total = (int)c;
-    // the candidates, PER per thread, in registers
-    uint64_t mine[PER];
-    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int x = tid + j * FIN_WG;
-        mine[j] = x < total ? cand[row * capg + x] : 0ull;
-        if (x < total) {
-            lo = min(lo, (uint32_t)(mine[j] >> 32));
-            hi = max(hi, (uint32_t)(mine[j] >> 32));
-        }
+    if (!ok) {
+        if (lane == 0) fail[row] = 1u;
+        return;
     }
-    hist[tid] = 0u;
-    if (tid == 0) {
-        range[0] = 0xFFFFFFFFu;
-        range[1] = 0u;
-        kept = 0;
+    uint32_t edge;
+    const int m = fin_cut<KEEP>(cand + row * (int64_t)capg, (int)c, need, need, buf, hist, edge);
+    if (m > KEEP) {
+        if (lane == 0) fail[row] = 1u;
+        return;
     }
-    __syncthreads();
-    int m = total;
-    if (total > need) {
-        // histogram of the score halves over [lo, hi] in 256 equal bins; the
-        // cut bin is the highest one with at least `need` keys in it and above,
-        // so every key of the best `need` is in a kept bin
-        atomicMin(&range[0], lo);
-        atomicMax(&range[1], hi);
-        __syncthreads();
-        const uint32_t L = range[0];
-        const uint64_t span = (uint64_t)(range[1] - L) + 1u;
-        auto bin_of = [&](uint64_t key) { return (int)(((uint64_t)((uint32_t)(key >> 32) - L) * FIN_BINS) / span); };
-#pragma unroll
-        for (int j = 0; j < PER; ++j)
-            if (tid + j * FIN_WG < total) atomicAdd(&hist[bin_of(mine[j])], 1u);
-        __syncthreads();
-        // suffix sums: thread t scans bin FIN_BINS - 1 - t
-        const int lane = tid % WAVE, wave = tid / WAVE;
-        uint32_t v = hist[FIN_BINS - 1 - tid];
-#pragma unroll
-        for (int d = 1; d < WAVE; d <<= 1) {
-            const uint32_t o = __shfl_up(v, d, WAVE);
-            if (lane >= d) v += o;
-        }
-        if (lane == WAVE - 1) wsum[wave] = v;
-        __syncthreads();
-        for (int w = 0; w < wave; ++w) v += wsum[w];
-        // bins 0 .. cut have suffix >= need
-        const int cut = __syncthreads_count(v >= (uint32_t)need) - 1;
-#pragma unroll
-        for (int j = 0; j < PER; ++j)
-            if (tid + j * FIN_WG < total && bin_of(mine[j]) >= cut) buf[atomicAdd(&kept, 1)] = mine[j];
-        __syncthreads();
-        m = kept;
-    } else {
-#pragma unroll
-        for (int j = 0; j < PER; ++j)
-            if (tid + j * FIN_WG < total) buf[tid + j * FIN_WG] = mine[j];
-        __syncthreads();
-    }
-    int lgN = 0;
-    while ((1 << lgN) < m) ++lgN;
-    const int half_n = (1 << lgN) >> 1;
-    // bitonic sort of buf[0 .. m), descending; pairs reaching past m are
-    // skipped (the missing keys act as the smallest)
-    for (int lp = 1; lp <= lgN; ++lp) {
-        const int lh = lp - 1;  // log2 of half the merged run
-        for (int idx = tid; idx < half_n; idx += FIN_WG) {
-            const int lo2 = idx & ((1 << lh) - 1);
-            const int x = ((idx >> lh) << lp) + lo2;
-            const int y = ((idx >> lh) << lp) + (1 << lp) - 1 - lo2;
-            if (y < m) {
-                const uint64_t a = buf[x], b2 = buf[y];
-                if (a < b2) {
-                    buf[x] = b2;
-                    buf[y] = a;
-                }
-            }
-        }
-        __syncthreads();
-        for (int lq = lh - 1; lq >= 0; --lq) {
-            for (int idx = tid; idx < half_n; idx += FIN_WG) {
-                const int x = ((idx >> lq) << (lq + 1)) + (idx & ((1 << lq) - 1));
-                const int y = x + (1 << lq);
-                if (y < m) {
-                    const uint64_t a = buf[x], b2 = buf[y];
-                    if (a < b2) {
-                        buf[x] = b2;
-                        buf[y] = a;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int j = tid; j < need; j += FIN_WG) sel[row * need + j] = j < m ? buf[j] : 0ull;
+    if (lane == 0) fail[row] = 0u;
+    wave_lds_fence();
+    wave_sort_desc(buf, m);
+    wave_lds_fence();
+    for (int j = lane; j < need; j += WAVE) sel[row * need + j] = j < m ? buf[j] : 0ull;
 }
 
 // Full selection for the users marked in fail[] (all items): each score is
@@ -618,60 +671,220 @@ __global__ __launch_bounds__(64) void score_select_kernel(const float *__restric
     }
 }
 
-// FP32 rescore of Kc candidates per user, then the best K.  One wave per
-// user; lane j takes candidates j, j + 64, ... and sums its dot product in a
-// fixed order (four fma chains over the factors f = 0, 1, 2, 3 mod 4, then
-// (c0 + c1) + (c2 + c3); the same every call), reading the user's row from
-// LDS.
-__global__ __launch_bounds__(64) void rescore_kernel(const uint64_t *__restrict__ cand, int Kc, int K,
-                                                     const float *__restrict__ Ug, int kp,
-                                                     const float *__restrict__ Qf, const float *__restrict__ bi,
-                                                     int k, uint64_t *__restrict__ out) {
-    __shared__ uint64_t buf[2048];
-    __shared__ __align__(16) float pu[256];
-    const int64_t row = blockIdx.x;
-    const int lane = threadIdx.x;
-    for (int f = lane; f < kp; f += WAVE) pu[f] = Ug[row * kp + f];
-    const bool vec = (k & 3) == 0;
-    for (int j = lane; j < Kc; j += WAVE) {
-        const uint64_t key = cand[row * Kc + j];
-        uint64_t nk = 0ull;
-        if (key != 0ull) {
-            const int32_t item = key_item(key);
-            const float *q = Qf + (int64_t)item * k;
-            float d = 0.f;
-            float c0 = 0.f, c1 = 0.f, c2 = 0.f, c3 = 0.f;
-            if (vec) {
-                for (int f = 0; f < k; f += 4) {
-                    const float4 qv = *reinterpret_cast<const float4 *>(q + f);
-                    c0 = fmaf(pu[f], qv.x, c0);
-                    c1 = fmaf(pu[f + 1], qv.y, c1);
-                    c2 = fmaf(pu[f + 2], qv.z, c2);
-                    c3 = fmaf(pu[f + 3], qv.w, c3);
-                }
-            } else {
-                for (int f = 0; f < k; f += 4) {
-                    c0 = fmaf(pu[f], q[f], c0);
-                    if (f + 1 < k) c1 = fmaf(pu[f + 1], q[f + 1], c1);
-                    if (f + 2 < k) c2 = fmaf(pu[f + 2], q[f + 2], c2);
-                    if (f + 3 < k) c3 = fmaf(pu[f + 3], q[f + 3], c3);
+// FP32 rescoring of BF16 candidates.  One wave per user; its four 16-lane
+// groups take one candidate each at a time, and lane l of a group multiplies
+// the factor chunks 4 (l + 16 c) .. + 3 (c = 0, 1, ...) in one fma chain,
+// then the group sums its lanes with the fixed butterfly of row16_sum.  A
+// candidate's item row is read by one group in one pass (16 lanes x 16
+// contiguous bytes per load), and the summation order is the same every
+// call and in both kernels below.
+constexpr int RS_MAXC = 4;  // chunks of four factors per lane: k <= 256
+constexpr int RS_U = 4;     // candidates per group in flight
+
+struct RescoreUser {
+    float4 pv[RS_MAXC];     // k % 4 == 0: this lane's chunks
+    float ps[4 * RS_MAXC];  // otherwise: factors l + 16 c
+    __device__ __forceinline__ void load(const float *__restrict__ Ug, int64_t row, int kp, int k, int l) {
+        if ((k & 3) == 0) {
+#pragma unroll
+            for (int c = 0; c < RS_MAXC; ++c) {
+                const int f = 4 * (l + 16 * c);
+                pv[c] = f < k ? *reinterpret_cast<const float4 *>(Ug + row * kp + f) : float4{0.f, 0.f, 0.f, 0.f};
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4 * RS_MAXC; ++c) {
+                const int f = l + 16 * c;
+                ps[c] = f < k ? Ug[row * kp + f] : 0.f;
+            }
+        }
+    }
+    // sum of squares of the row (every lane of a group gets the same value)
+    __device__ __forceinline__ float sq(int k) const {
+        float v = 0.f;
+        if ((k & 3) == 0) {
+#pragma unroll
+            for (int c = 0; c < RS_MAXC; ++c) v += pv[c].x * pv[c].x + pv[c].y * pv[c].y + pv[c].z * pv[c].z + pv[c].w * pv[c].w;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 4 * RS_MAXC; ++c) v += ps[c] * ps[c];
+        }
+        return row16_sum(v);
+    }
+};
+
+// Rescored keys of candidates src[j] (j = 4 t + group < R) into dst[j]
+// (src and dst may be the same LDS array: a group reads its key before it
+// writes the new one at the same position).  Empty keys (0) stay 0.
+__device__ __forceinline__ void rescore_keys(const RescoreUser &P, const uint64_t *src, uint64_t *dst, int R,
+                                             const float *__restrict__ Qf, const float *__restrict__ bi, int k) {
+    const int lane = threadIdx.x, g = lane >> 4, l = lane & 15;
+    if ((k & 3) == 0) {
+        for (int j0 = 0; j0 < R; j0 += 4 * RS_U) {
+            uint64_t key[RS_U];
+#pragma unroll
+            for (int u = 0; u < RS_U; ++u) {
+                const int j = j0 + 4 * u + g;
+                key[u] = j < R ? src[j] : 0ull;
+            }
+            float4 q[RS_U][RS_MAXC];
+#pragma unroll
+            for (int u = 0; u < RS_U; ++u) {
+                const float *qr = Qf + (int64_t)(key[u] != 0ull ? key_item(key[u]) : 0) * k;
+#pragma unroll
+                for (int c = 0; c < RS_MAXC; ++c) {
+                    const int f = 4 * (l + 16 * c);
+                    q[u][c] = (key[u] != 0ull && f < k) ? *reinterpret_cast<const float4 *>(qr + f)
+                                                        : float4{0.f, 0.f, 0.f, 0.f};
                 }
             }
-            d = (c0 + c1) + (c2 + c3);
-            nk = rank_key(d + bi[item], item);
+#pragma unroll
+            for (int u = 0; u < RS_U; ++u) {
+                float d = 0.f;
+#pragma unroll
+                for (int c = 0; c < RS_MAXC; ++c) {
+                    d = fmaf(P.pv[c].x, q[u][c].x, d);
+                    d = fmaf(P.pv[c].y, q[u][c].y, d);
+                    d = fmaf(P.pv[c].z, q[u][c].z, d);
+                    d = fmaf(P.pv[c].w, q[u][c].w, d);
+                }
+                d = row16_sum(d);
+                const int j = j0 + 4 * u + g;
+                if (l == 0 && j < R) {
+                    const int32_t item = key_item(key[u]);
+                    dst[j] = key[u] != 0ull ? rank_key(d + bi[item], item) : 0ull;
+                }
+            }
         }
-        buf[j] = nk;
+    } else {
+        for (int j0 = 0; j0 < R; j0 += 4) {
+            const int j = j0 + g;
+            const uint64_t key = j < R ? src[j] : 0ull;
+            const float *qr = Qf + (int64_t)(key != 0ull ? key_item(key) : 0) * k;
+            float d = 0.f;
+#pragma unroll
+            for (int c = 0; c < 4 * RS_MAXC; ++c) {
+                const int f = l + 16 * c;
+                if (key != 0ull && f < k) d = fmaf(P.ps[c], qr[f], d);
+            }
+            d = row16_sum(d);
+            if (l == 0 && j < R) {
+                const int32_t item = key_item(key);
+                dst[j] = key != 0ull ? rank_key(d + bi[item], item) : 0ull;
+            }
+        }
     }
-    wave_sort_desc(buf, Kc);
-    for (int j = lane; j < K; j += WAVE) out[row * K + j] = j < Kc ? buf[j] : 0ull;
 }
 
-__global__ void decode_kernel(const uint64_t *__restrict__ keys, int64_t nu, int K, const float *__restrict__ ub,
-                              int32_t *__restrict__ items, float *__restrict__ scores) {
+// Rescore of the users marked in fail[] (their Kc BF16 keys at sel + row *
+// Kc, from the full selection), then their best K in place at sel + row *
+// Kc.  Users not marked were finished by finish_rescore_kernel.
+__global__ __launch_bounds__(64) void rescore_kernel(uint64_t *__restrict__ sel, int Kc, int K,
+                                                     const uint32_t *__restrict__ fail,
+                                                     const float *__restrict__ Ug, int kp,
+                                                     const float *__restrict__ Qf, const float *__restrict__ bi,
+                                                     int k) {
+    __shared__ uint64_t buf[FIN_KEEP];  // Kc <= 1008
+    const int64_t row = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (fail[row] == 0u) return;
+    RescoreUser P;
+    P.load(Ug, row, kp, k, lane & 15);
+    uint64_t *keys = sel + row * (int64_t)Kc;
+    rescore_keys(P, keys, buf, Kc, Qf, bi, k);
+    wave_lds_fence();
+    wave_sort_desc(buf, Kc);
+    wave_lds_fence();
+    for (int j = lane; j < K; j += WAVE) keys[j] = j < Kc ? buf[j] : 0ull;
+}
+
+// BF16 path, passes 3 and 4 in one: the histogram cut keeps the candidates
+// that can be among the best Kc BF16 keys, and of those only the ones that
+// can still reach the FP32 top K are rescored.  With B a BF16 score (the
+// filter's) and F the FP32 score of the same item, |B - F| <= eps, where eps
+// bounds the rounding of both operands to BF16 (relative 2^-9 each) and the
+// FP32 accumulation in both kernels:
+//   eps = (2^-8 (1.01) + 4 (k + 2) 2^-24) ||p|| max_j ||q_j|| + 4 (k + 2) 2^-24 max_j |b_j|,
+// inflated by 1%.  If T is the K-th best BF16 score among the candidates, K
+// of them have F >= T - eps, so a candidate with B < T - 2 eps has
+// F < T - eps and is not in the FP32 top K of the best Kc; it is dropped.
+// T is bounded below by the lower edge of the histogram bin holding the
+// K-th best key.  The kept keys above that bound form a prefix of the key
+// order; when there are at most Kc of them they are all among the best Kc
+// and only they are rescored, otherwise the best Kc are found by a sort and
+// rescored.  The result equals rescoring all Kc.  A user that the cut
+// cannot handle is marked in fail[] for the full selection and
+// rescore_kernel.  The best K keys go to sel + row * Kc.
+template <int KEEP>
+__global__ __launch_bounds__(FIN_WG) void finish_rescore_kernel(
+    const uint32_t *__restrict__ thr, const uint32_t *__restrict__ cnt, const uint64_t *__restrict__ cand, int capg,
+    int Kc, int K, const float *__restrict__ Ug, int kp, const float *__restrict__ Qf, const float *__restrict__ bi,
+    int k, const float *__restrict__ stats, int prune, uint32_t *__restrict__ fail, uint64_t *__restrict__ sel) {
+    __shared__ uint64_t buf[KEEP];
+    __shared__ uint32_t hist[FIN_BINS];
+    const int lane = threadIdx.x;
+    const int64_t row = blockIdx.x;
+    const uint32_t c = cnt[row];
+    const bool ok = c <= (uint32_t)capg && (c >= (uint32_t)Kc || thr[row] == 0u);
+    if (!ok) {
+        if (lane == 0) fail[row] = 1u;
+        return;
+    }
+    uint32_t edge;
+    const int m = fin_cut<KEEP>(cand + row * (int64_t)capg, (int)c, Kc, K, buf, hist, edge);
+    if (m > KEEP) {
+        if (lane == 0) fail[row] = 1u;
+        return;
+    }
+    if (lane == 0) fail[row] = 0u;
+    RescoreUser P;
+    P.load(Ug, row, kp, k, lane & 15);
+    // the drop bound (no drop without a histogram edge or when turned off)
+    float lim = -INFINITY;
+    if (prune && edge != 0u) {
+        const float g = 4.f * (float)(k + 2) * 0x1p-24f;
+        const float eps = 1.01f * ((0x1p-8f * 1.01f + g) * sqrtf(P.sq(k)) * 1.0001f * stats[0] + g * stats[1]) + 1e-30f;
+        const float t = ordered_to_float(edge);
+        lim = t - 2.f * eps - fabsf(t) * 0x1p-20f;
+        if (!(lim == lim)) lim = -INFINITY;
+    }
+    wave_lds_fence();
+    // keep the keys at or above lim at the front of buf, in place (a chunk's
+    // keys move to positions below the next chunk's)
+    int u = 0;
+    for (int x0 = 0; x0 < m; x0 += WAVE) {
+        const int x = x0 + lane;
+        const uint64_t key = x < m ? buf[x] : 0ull;
+        const bool keep = x < m && !(key_score(key) < lim);
+        const uint64_t bal = __ballot(keep);
+        const int at = u + __popcll(bal & ((1ull << lane) - 1ull));
+        wave_lds_fence();
+        if (keep) buf[at] = key;
+        u += __popcll(bal);
+    }
+    wave_lds_fence();
+    int R = u;
+    if (u > Kc) {
+        wave_sort_desc(buf, u);
+        wave_lds_fence();
+        R = Kc;
+    }
+    rescore_keys(P, buf, buf, R, Qf, bi, k);
+    wave_lds_fence();
+    wave_sort_desc(buf, R);
+    wave_lds_fence();
+    uint64_t *o = sel + row * (int64_t)Kc;
+    for (int j = lane; j < K; j += WAVE) o[j] = j < R ? buf[j] : 0ull;
+}
+
+// The best K keys of user q at keys + q * stride to items and scores (the
+// user's offset mu + bu added back; -1 / -inf for empty keys).
+__global__ void decode_kernel(const uint64_t *__restrict__ keys, int64_t nu, int K, int stride,
+                              const float *__restrict__ ub, int32_t *__restrict__ items, float *__restrict__ scores) {
     const int64_t total = nu * K;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t q = t / K;
-        const uint64_t key = keys[t];
+        const uint64_t key = keys[q * stride + (t - q * K)];
         const float off = ub[q];
         if (key == 0ull || off != off) {
             items[t] = -1;
@@ -693,24 +906,33 @@ static int cap_for(int K) {
 // Pass kernels of one request for the given latent chunk count KC.
 template <int KC, bool BF16>
 static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ugb, const float *Qf,
-                          const uint16_t *Qb, const float *bi, int64_t n, int k, uint32_t *thr, uint32_t *cnt,
-                          uint32_t *fail, uint64_t *cand, uint64_t *sel, hipStream_t s) {
+                          const uint16_t *Qb, const float *bi, int64_t n, int k, const float *stats, uint32_t *thr,
+                          uint32_t *cnt, uint32_t *fail, uint64_t *cand, uint64_t *sel, hipStream_t s) {
     const unsigned tiles = (unsigned)(T.nu_pad / TU);
     sample_threshold_kernel<KC, BF16><<<tiles, SMP_WAVES * WAVE, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb, T.s, T.r, thr, cnt);
     BMF_HIP(hipGetLastError());
     constexpr int UT = filter_tiles_per_wave(KC, BF16);
     if (T.ut != UT) BMF_FAIL(BMF_E_STATE, "top-K plan made for another filter shape");
     const unsigned groups = (unsigned)((tiles + UT - 1) / UT);
-    filter_kernel<KC, BF16, UT><<<dim3(groups, (unsigned)T.S), 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb,
-                                                                          (int64_t)tiles, T.per_split, thr, cnt,
-                                                                          T.capg, cand);
+    filter_kernel<KC, BF16, UT><<<groups * (unsigned)T.S, 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb,
+                                                                     (int64_t)tiles, T.per_split, T.S, thr, cnt,
+                                                                     T.capg, cand);
     BMF_HIP(hipGetLastError());
-    if (T.capg <= 1024)
-        finish_kernel<1024><<<(unsigned)T.nu_pad, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, fail, sel);
-    else if (T.capg <= 2048)
-        finish_kernel<2048><<<(unsigned)T.nu_pad, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, fail, sel);
-    else
-        finish_kernel<CAPG_MAX><<<(unsigned)T.nu_pad, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, fail, sel);
+    const unsigned rows = (unsigned)T.nu_pad;
+    const bool small = T.Ksel <= FIN_KEEP_SMALL_NEED;
+    if (BF16) {
+        if (small)
+            finish_rescore_kernel<FIN_KEEP_SMALL><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, T.K, Ug, T.kp,
+                                                                         Qf, bi, k, stats, T.prune, fail, sel);
+        else
+            finish_rescore_kernel<FIN_KEEP><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, T.K, Ug, T.kp, Qf,
+                                                                   bi, k, stats, T.prune, fail, sel);
+    } else {
+        if (small)
+            finish_kernel<FIN_KEEP_SMALL><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, fail, sel);
+        else
+            finish_kernel<FIN_KEEP><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, fail, sel);
+    }
     BMF_HIP(hipGetLastError());
     switch (cap_for(T.Ksel)) {
     case 256:
@@ -725,20 +947,25 @@ static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ug
         break;
     }
     BMF_HIP(hipGetLastError());
+    if (BF16) {
+        // the users the full selection redid
+        rescore_kernel<<<(unsigned)T.nu, 64, 0, s>>>(sel, T.Ksel, T.K, fail, Ug, T.kp, Qf, bi, k);
+        BMF_HIP(hipGetLastError());
+    }
 }
 
 template <bool BF16>
 static void passes_dispatch(int kc, const TopkPlan &T, const float *Ug, const uint16_t *Ugb, const float *Qf,
-                            const uint16_t *Qb, const float *bi, int64_t n, int k, uint32_t *thr, uint32_t *cnt,
-                            uint32_t *fail, uint64_t *cand, uint64_t *sel, hipStream_t s) {
+                            const uint16_t *Qb, const float *bi, int64_t n, int k, const float *stats, uint32_t *thr,
+                            uint32_t *cnt, uint32_t *fail, uint64_t *cand, uint64_t *sel, hipStream_t s) {
     switch (kc) {
-    case 1: launch_passes<1, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, thr, cnt, fail, cand, sel, s); break;
-    case 2: launch_passes<2, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, thr, cnt, fail, cand, sel, s); break;
+    case 1: launch_passes<1, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, stats, thr, cnt, fail, cand, sel, s); break;
+    case 2: launch_passes<2, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, stats, thr, cnt, fail, cand, sel, s); break;
     case 3:
-    case 4: launch_passes<4, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, thr, cnt, fail, cand, sel, s); break;
+    case 4: launch_passes<4, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, stats, thr, cnt, fail, cand, sel, s); break;
     case 5: case 6: case 7:
-    case 8: launch_passes<8, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, thr, cnt, fail, cand, sel, s); break;
-    default: launch_passes<16, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, thr, cnt, fail, cand, sel, s); break;
+    case 8: launch_passes<8, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, stats, thr, cnt, fail, cand, sel, s); break;
+    default: launch_passes<16, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, stats, thr, cnt, fail, cand, sel, s); break;
     }
 }
 
@@ -758,10 +985,17 @@ static int sample_rank(double lambda, double eps) {
     return r;
 }
 
+// The BF16 item table, followed (at the next 256-byte boundary) by two
+// floats: an upper bound on the item rows' 2-norms and the largest |bias|.
+static size_t bf16_table_bytes(const Model &M) { return ((size_t)M.n * round_up(M.k, 32) * 2 + 255) & ~size_t(255); }
+static float *bf16_item_stats(Model &M) {
+    return reinterpret_cast<float *>(M.Qb.as<unsigned char>() + bf16_table_bytes(M));
+}
+
 void ensure_bf16_items(Model &M, bool may_alloc) {
     if (M.bf16_valid) return;
     const int kb = round_up(M.k, 32);
-    const size_t need = (size_t)M.n * kb * sizeof(uint16_t);
+    const size_t need = bf16_table_bytes(M) + 256;
     if (M.Qb.bytes < need) {
         if (!may_alloc)
             BMF_FAIL(BMF_E_STATE, "the BF16 item table has no device memory yet: run one BF16 top-K call that may "
@@ -770,6 +1004,12 @@ void ensure_bf16_items(Model &M, bool may_alloc) {
     }
     const int grid = (int)std::min<int64_t>((M.n * kb + 255) / 256, 8192);
     bf16_table_kernel<<<grid, 256, 0, M.stream>>>(M.Q.as<float>(), M.n, M.k, kb, M.Qb.as<uint16_t>());
+    BMF_HIP(hipGetLastError());
+    float *st = bf16_item_stats(M);
+    item_stats_clear_kernel<<<1, 64, 0, M.stream>>>(st);
+    BMF_HIP(hipGetLastError());
+    const int sgrid = (int)std::min<int64_t>((M.n + 255) / 256, 4096);
+    item_stats_kernel<<<sgrid, 256, 0, M.stream>>>(M.Q.as<float>(), M.bi.as<float>(), M.n, M.k, st);
     BMF_HIP(hipGetLastError());
     M.bf16_valid = true;
 }
@@ -780,6 +1020,10 @@ TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
     T.K = K;
     T.bf = precision == 1;
     T.Ksel = T.bf ? topk_candidates(K, Kc) : K;
+    {
+        const char *e = std::getenv("BMF_TOPK_PRUNE");
+        T.prune = (e && e[0] == '0' && e[1] == 0) ? 0 : 1;
+    }
     if (K < 1 || T.Ksel > 1008) BMF_FAIL(BMF_E_INVAL, "top-K needs 1 <= K and at most 1008 candidates per user");
     T.kp = round_up(M.k, 16);
     T.kb = round_up(M.k, 32);
@@ -801,12 +1045,19 @@ TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
         T.capg = std::min(CAPG_MAX, round_up((int)std::min(3.0 * expect + 128.0, (double)CAPG_MAX), 64));
         T.capg = std::max(T.capg, std::min(CAPG_MAX, round_up(need + 64, 64)));
     }
-    // item splits for the filter: enough workgroups to fill the chip
+    // item splits for the filter: enough workgroups to fill the chip, and a
+    // multiple of 8 (one eighth of the item rows per XCD) where every split
+    // still holds at least 256 items
     T.ut = filter_tiles_per_wave(dispatch_kc(T.bf ? T.kb / 32 : T.kp / 16), T.bf);
     const int64_t groups = (T.nu_pad / TU + T.ut - 1) / T.ut;
     int S = (int)std::max<int64_t>(1, (4096 + groups - 1) / std::max<int64_t>(groups, 1));
+    if (n >= 8 * 256) S = round_up(S, 8);
     S = (int)std::min<int64_t>(S, std::max<int64_t>(1, n / 256));
+    // the filter's lists hold item offsets in 16 bits: at most 65520 items
+    // (a multiple of the tile) per split
+    S = (int)std::max<int64_t>(S, (n + 65519) / 65520);
     T.per_split = ((n + S - 1) / S + TI - 1) / TI * TI;
+    if (T.per_split > 65536) BMF_FAIL(BMF_E_INVAL, "too many items for the top-K filter's splits");
     T.S = (int)std::max<int64_t>(1, (n + T.per_split - 1) / T.per_split);
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -848,21 +1099,14 @@ void topk_score(Model &M, const TopkPlan &T, unsigned char *work, int32_t *d_ite
     if (T.bf) {
         if (!M.bf16_valid) BMF_FAIL(BMF_E_STATE, "BF16 item table not prepared");
         passes_dispatch<true>(T.kb / 32, T, Ug, Ugb, M.Q.as<float>(), M.Qb.as<uint16_t>(), M.bi.as<float>(), M.n, M.k,
-                              thr, cnt, fail, cand, sel, s);
+                              bf16_item_stats(M), thr, cnt, fail, cand, sel, s);
     } else {
-        passes_dispatch<false>(T.kp / 16, T, Ug, Ugb, M.Q.as<float>(), nullptr, M.bi.as<float>(), M.n, M.k, thr, cnt,
-                               fail, cand, sel, s);
+        passes_dispatch<false>(T.kp / 16, T, Ug, Ugb, M.Q.as<float>(), nullptr, M.bi.as<float>(), M.n, M.k, nullptr,
+                               thr, cnt, fail, cand, sel, s);
     }
-    const uint64_t *fin = sel;
-    if (T.bf) {
-        uint64_t *dst = cand;  // the candidate buffers are free again
-        rescore_kernel<<<(unsigned)T.nu, 64, 0, s>>>(sel, T.Ksel, T.K, Ug, T.kp, M.Q.as<float>(), M.bi.as<float>(), M.k,
-                                                    dst);
-        BMF_HIP(hipGetLastError());
-        fin = dst;
-    }
+    // every user's best K keys are at sel + row * Ksel
     const int dgrid = (int)std::min<int64_t>((T.nu * T.K + 255) / 256, 8192);
-    decode_kernel<<<dgrid, 256, 0, s>>>(fin, T.nu, T.K, ub, d_items, d_scores);
+    decode_kernel<<<dgrid, 256, 0, s>>>(sel, T.nu, T.K, T.Ksel, ub, d_items, d_scores);
     BMF_HIP(hipGetLastError());
 }
 

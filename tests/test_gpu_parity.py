@@ -412,6 +412,51 @@ def test_topk_bf16_recall_and_rescore(B, orc, k):
     eps_valid(bi_, bs, P, Q, bu, bi, 3.5, users, K, (k + 8) * 2.0 ** -23)
 
 
+@pytest.mark.parametrize("scale,k,Kc", [(0.02, 128, 0), (0.3, 128, 0), (0.05, 64, 300), (0.02, 13, 0)])
+def test_topk_bf16_candidate_drop_changes_nothing(B, monkeypatch, scale, k, Kc):
+    """The BF16 path drops candidates whose BF16 score lies more than twice
+    the rounding bound below the K-th best before rescoring; the answer must
+    equal rescoring every one of the Kc candidates (BMF_TOPK_PRUNE=0), bit for
+    bit.  Small factors against a wider bias spread (as after a few epochs)
+    make the drop take most of the extra candidates; scale 0.3 leaves most."""
+    rng = np.random.default_rng(int(scale * 1000) + k)
+    m, n, K = 300, 17800, 100
+    P = rng.normal(0, scale, (m, k)).astype(np.float32)
+    Q = rng.normal(0, 0.3, (n, k)).astype(np.float32)
+    bu = rng.normal(0, 0.3, m).astype(np.float32)
+    bi = rng.normal(0, 0.3, n).astype(np.float32)
+    G = B.Model(m, n, k, 4)
+    G.set_factors(P, Q, bu, bi, 3.5)
+    users = np.arange(m, dtype=np.int32)
+    monkeypatch.delenv("BMF_TOPK_PRUNE", raising=False)
+    a_i, a_s = G.topk_bf16(users, K, Kc=Kc)
+    monkeypatch.setenv("BMF_TOPK_PRUNE", "0")
+    b_i, b_s = G.topk_bf16(users, K, Kc=Kc)
+    assert np.array_equal(a_i, b_i)
+    assert np.array_equal(a_s.view(np.uint32), b_s.view(np.uint32))
+    eps_valid(a_i, a_s, P, Q, bu, bi, 3.5, users, K, (k + 8) * 2.0 ** -23)
+
+
+def test_topk_bf16_crowded_scores_take_the_full_selection(B):
+    """700 items share the best score exactly (zero user factors, equal
+    biases): the histogram cannot split them, so those users go through the
+    full selection and its rescore; the answer is the 100 smallest of those
+    item ids in both precisions."""
+    m, n, k, K = 40, 17800, 128, 100
+    rng = np.random.default_rng(8)
+    Q = rng.normal(0, 0.3, (n, k)).astype(np.float32)
+    bi = np.zeros(n, np.float32)
+    top = np.sort(rng.choice(n, 700, replace=False))
+    bi[top] = 1.0
+    G = B.Model(m, n, k, 4)
+    G.set_factors(np.zeros((m, k), np.float32), Q, np.zeros(m, np.float32), bi, 0.0)
+    users = np.arange(m, dtype=np.int32)
+    for fn in (G.topk, G.topk_bf16):
+        items, scores = fn(users, K)
+        assert np.all(items == top[:K][None, :])
+        assert np.all(scores == 1.0)
+
+
 # ---------------------------------------------------------------- fold-in
 @pytest.mark.parametrize("k,nr", [(128, 5), (128, 500), (64, 37), (13, 100), (256, 300), (1000, 60)])
 def test_foldin_matches_oracle(B, orc, k, nr):

@@ -93,7 +93,11 @@ typedef enum {
      * copies groups of strata (up to 8, at most 64 MiB when a stratum is
      * smaller, else one) in the epoch's order into a ring of three device
      * buffers on a copy stream while earlier groups run.  Device memory then
-     * holds the factor tables and three such groups.  The kernels, and so the results, are
+     * holds the factor tables and three such groups.  An out-of-core epoch
+     * call waits on the host until a ring buffer is free before it queues the
+     * copy into it, so it returns when its last group is queued (about two
+     * groups before the epoch ends), and it cannot be captured into a HIP
+     * graph.  The kernels, and so the results, are
      * those of a resident load with the same SGD kernel; mu is summed on the
      * host in input order.  Such a load takes host arrays only
      * (bmf_load_ratings), fixes the SGD kernel (set BMF_OPT_SGD_KERNEL before

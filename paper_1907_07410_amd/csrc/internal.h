@@ -143,6 +143,7 @@ struct OutOfCore {
     hipStream_t copy = nullptr;
     hipEvent_t copied[OOC_BUFS] = {}, used[OOC_BUFS] = {};
     bool used_valid[OOC_BUFS] = {};
+    int64_t ring = 0;  // groups sent so far: the next one goes to buffer ring % OOC_BUFS
     void release();
     ~OutOfCore() { release(); }
 };

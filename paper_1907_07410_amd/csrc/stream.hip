@@ -51,6 +51,7 @@ void OutOfCore::release() {
     std::vector<int32_t>().swap(perm);
     s_off.clear();
     s_units.clear();
+    ring = 0;
     on = false;
 }
 
@@ -243,10 +244,25 @@ void ooc_load(Model &M, const int32_t *u, const int32_t *i, const float *r, int6
 void ooc_epoch(Model &M, const int32_t *order, const HP &hp, int variant) {
     OutOfCore &X = M.ooc;
     const int b = M.b;
-    for (int g0 = 0, gi = 0; g0 < b; g0 += X.group, ++gi) {
-        const int g1 = std::min(b, g0 + X.group), q = gi % OOC_BUFS;
-        // the buffer is free once the kernels that last read it have finished
-        if (X.used_valid[q]) BMF_HIP(hipStreamWaitEvent(X.copy, X.used[q], 0));
+    // groups of 1 and 3 strata start the epoch, so that the copy a kernel
+    // waits for at the start of an epoch (when nothing of it was queued
+    // before) is one stratum's, and each next copy fits under the kernels
+    // queued before it; then groups of X.group
+    for (int g0 = 0, g1 = 0, gi = 0; g0 < b; g0 = g1, ++gi) {
+        g1 = std::min(b, g0 + std::min(X.group, gi == 0 ? 1 : gi == 1 ? 3 : X.group));
+        // the ring runs on across epochs, so an epoch's first copies go to
+        // buffers the previous epoch's last kernels do not read
+        const int q = (int)(X.ring++ % OOC_BUFS);
+        // the buffer is free once the kernels that last read it have
+        // finished.  The host waits for that before it queues the copy: with
+        // the copies of later groups and epochs queued far ahead behind
+        // cross-stream waits, single stratum launches took 1.3-2.4 ms instead
+        // of 0.27 (about one epoch in two 1-3 ms slower); queued only when
+        // the buffer is free, every epoch runs at the resident pace.
+        if (X.used_valid[q]) {
+            BMF_HIP(hipEventSynchronize(X.used[q]));
+            BMF_HIP(hipStreamWaitEvent(X.copy, X.used[q], 0));
+        }
         // the group's strata back to back (each its units and its block table
         // behind them), one copy per run of strata adjacent in host memory
         unsigned char *dst = X.stage[q].as<unsigned char>();

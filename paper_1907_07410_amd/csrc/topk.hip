@@ -258,12 +258,14 @@ constexpr int SAMPLE_MAX = 1024;
 // Stored as an ordered key; 0 = no threshold (r = 0).  Also clears the
 // user's candidate count.  One workgroup of SMP_WAVES waves per 16-user tile,
 // each wave taking every SMP_WAVES-th sample tile in the sweep; lane (u, g)
-// holds user u's scores.
+// holds user u's scores.  The BF16 form fits 64 registers (no row prefetch),
+// so two workgroups share a CU and one's selection overlaps the other's
+// sweep.
 constexpr int SMP_WAVES = 16;
 static_assert(SMP_WAVES == TU, "one wave per user of the tile selects its threshold");
 
 template <int KC, bool BF16>
-__global__ __launch_bounds__(SMP_WAVES *WAVE) void sample_threshold_kernel(
+__global__ __launch_bounds__(SMP_WAVES *WAVE, BF16 ? 8 : 4) void sample_threshold_kernel(
     const float *__restrict__ Ug, const uint16_t *__restrict__ Ugb, const float *__restrict__ Qf,
     const uint16_t *__restrict__ Qb, const float *__restrict__ bi, int64_t n, int k, int kp, int kb, int s, int r,
     uint32_t *__restrict__ thr, uint32_t *__restrict__ cnt) {
@@ -288,7 +290,21 @@ __global__ __launch_bounds__(SMP_WAVES *WAVE) void sample_threshold_kernel(
     };
     // the wave's sample tiles, the next tile's rows loaded while the current
     // one is multiplied
-    {
+    if (BF16) {
+        for (int t0 = wave * TI; t0 < s; t0 += step) {
+            ItemFrag<KC, BF16> A;
+            float b[4];
+            const int ta = t0 + ucol;
+            A.load(Qf, Qb, (int64_t)ta * n / s, ta < s, k, kb, grp);
+            sample_bias(t0, b);
+            const f32x4 acc = tile_mma(U, A, f32x4{b[0], b[1], b[2], b[3]});
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int t = t0 + 4 * grp + rr;
+                if (t < s) keys[ucol][t] = float_to_ordered(acc[rr]);
+            }
+        }
+    } else {
         ItemFrag<KC, BF16> A, An;
         float b[4], bn[4];
         int t0 = wave * TI;
@@ -678,9 +694,10 @@ __global__ __launch_bounds__(64) void score_select_kernel(const float *__restric
 // candidate's item row is read by one group in one pass (16 lanes x 16
 // contiguous bytes per load), and the summation order is the same every
 // call and in both kernels below.
-constexpr int RS_MAXC = 4;  // chunks of four factors per lane: k <= 256
-constexpr int RS_U = 4;     // candidates per group in flight
-
+// RS_MAXC chunks of four factors per lane cover k <= 64 RS_MAXC; RS_U
+// candidates per group are in flight.  Two forms: k <= 128 (2 chunks, 8
+// candidates in flight) and k <= 256 (4 chunks, 4 in flight).
+template <int RS_MAXC>
 struct RescoreUser {
     float4 pv[RS_MAXC];     // k % 4 == 0: this lane's chunks
     float ps[4 * RS_MAXC];  // otherwise: factors l + 16 c
@@ -716,8 +733,10 @@ struct RescoreUser {
 // Rescored keys of candidates src[j] (j = 4 t + group < R) into dst[j]
 // (src and dst may be the same LDS array: a group reads its key before it
 // writes the new one at the same position).  Empty keys (0) stay 0.
-__device__ __forceinline__ void rescore_keys(const RescoreUser &P, const uint64_t *src, uint64_t *dst, int R,
+template <int RS_MAXC>
+__device__ __forceinline__ void rescore_keys(const RescoreUser<RS_MAXC> &P, const uint64_t *src, uint64_t *dst, int R,
                                              const float *__restrict__ Qf, const float *__restrict__ bi, int k) {
+    constexpr int RS_U = RS_MAXC <= 2 ? 8 : 4;
     const int lane = threadIdx.x, g = lane >> 4, l = lane & 15;
     if ((k & 3) == 0) {
         for (int j0 = 0; j0 < R; j0 += 4 * RS_U) {
@@ -779,6 +798,7 @@ __device__ __forceinline__ void rescore_keys(const RescoreUser &P, const uint64_
 // Rescore of the users marked in fail[] (their Kc BF16 keys at sel + row *
 // Kc, from the full selection), then their best K in place at sel + row *
 // Kc.  Users not marked were finished by finish_rescore_kernel.
+template <int RS_MAXC>
 __global__ __launch_bounds__(64) void rescore_kernel(uint64_t *__restrict__ sel, int Kc, int K,
                                                      const uint32_t *__restrict__ fail,
                                                      const float *__restrict__ Ug, int kp,
@@ -788,7 +808,7 @@ __global__ __launch_bounds__(64) void rescore_kernel(uint64_t *__restrict__ sel,
     const int64_t row = blockIdx.x;
     const int lane = threadIdx.x;
     if (fail[row] == 0u) return;
-    RescoreUser P;
+    RescoreUser<RS_MAXC> P;
     P.load(Ug, row, kp, k, lane & 15);
     uint64_t *keys = sel + row * (int64_t)Kc;
     rescore_keys(P, keys, buf, Kc, Qf, bi, k);
@@ -815,7 +835,7 @@ __global__ __launch_bounds__(64) void rescore_kernel(uint64_t *__restrict__ sel,
 // rescored.  The result equals rescoring all Kc.  A user that the cut
 // cannot handle is marked in fail[] for the full selection and
 // rescore_kernel.  The best K keys go to sel + row * Kc.
-template <int KEEP>
+template <int KEEP, int RS_MAXC>
 __global__ __launch_bounds__(FIN_WG) void finish_rescore_kernel(
     const uint32_t *__restrict__ thr, const uint32_t *__restrict__ cnt, const uint64_t *__restrict__ cand, int capg,
     int Kc, int K, const float *__restrict__ Ug, int kp, const float *__restrict__ Qf, const float *__restrict__ bi,
@@ -837,7 +857,7 @@ __global__ __launch_bounds__(FIN_WG) void finish_rescore_kernel(
         return;
     }
     if (lane == 0) fail[row] = 0u;
-    RescoreUser P;
+    RescoreUser<RS_MAXC> P;
     P.load(Ug, row, kp, k, lane & 15);
     // the drop bound (no drop without a histogram edge or when turned off)
     float lim = -INFINITY;
@@ -921,12 +941,19 @@ static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ug
     const unsigned rows = (unsigned)T.nu_pad;
     const bool small = T.Ksel <= FIN_KEEP_SMALL_NEED;
     if (BF16) {
-        if (small)
-            finish_rescore_kernel<FIN_KEEP_SMALL><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, T.K, Ug, T.kp,
-                                                                         Qf, bi, k, stats, T.prune, fail, sel);
+        const bool k128 = k <= 128;
+        if (small && k128)
+            finish_rescore_kernel<FIN_KEEP_SMALL, 2><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, T.K, Ug,
+                                                                            T.kp, Qf, bi, k, stats, T.prune, fail, sel);
+        else if (small)
+            finish_rescore_kernel<FIN_KEEP_SMALL, 4><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, T.K, Ug,
+                                                                            T.kp, Qf, bi, k, stats, T.prune, fail, sel);
+        else if (k128)
+            finish_rescore_kernel<FIN_KEEP, 2><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, T.K, Ug, T.kp,
+                                                                      Qf, bi, k, stats, T.prune, fail, sel);
         else
-            finish_rescore_kernel<FIN_KEEP><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, T.K, Ug, T.kp, Qf,
-                                                                   bi, k, stats, T.prune, fail, sel);
+            finish_rescore_kernel<FIN_KEEP, 4><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, T.K, Ug, T.kp,
+                                                                      Qf, bi, k, stats, T.prune, fail, sel);
     } else {
         if (small)
             finish_kernel<FIN_KEEP_SMALL><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, fail, sel);
@@ -949,7 +976,10 @@ static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ug
     BMF_HIP(hipGetLastError());
     if (BF16) {
         // the users the full selection redid
-        rescore_kernel<<<(unsigned)T.nu, 64, 0, s>>>(sel, T.Ksel, T.K, fail, Ug, T.kp, Qf, bi, k);
+        if (k <= 128)
+            rescore_kernel<2><<<(unsigned)T.nu, 64, 0, s>>>(sel, T.Ksel, T.K, fail, Ug, T.kp, Qf, bi, k);
+        else
+            rescore_kernel<4><<<(unsigned)T.nu, 64, 0, s>>>(sel, T.Ksel, T.K, fail, Ug, T.kp, Qf, bi, k);
         BMF_HIP(hipGetLastError());
     }
 }

@@ -98,16 +98,31 @@ __global__ void gather_users_kernel(const int32_t *__restrict__ users, int64_t n
                                     const float *__restrict__ P, const float *__restrict__ bu, float mu, int k,
                                     int kp, int kb, float *__restrict__ Ug, uint16_t *__restrict__ Ugb,
                                     float *__restrict__ ub) {
-    const int64_t total = nu_pad * kb;
-    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t q = t / kb;
-        const int f = (int)(t % kb);
+    // one wave per row, four factors per lane per turn (kp and kb are
+    // multiples of 16 and 32, so a lane's four stay inside both rows)
+    const int lane = threadIdx.x % WAVE;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    for (int64_t q = w0; q < nu_pad; q += nw) {
         const int64_t u = q < nu ? (int64_t)users[q] : -1;
         const bool ok = u >= 0 && u < m;
-        const float v = (ok && f < k) ? P[u * k + f] : 0.f;
-        if (f < kp) Ug[q * kp + f] = v;
-        if (Ugb) Ugb[q * kb + f] = to_bf16_rne(v);
-        if (f == 0) ub[q] = ok ? mu + bu[u] : __int_as_float(0x7fc00000);
+        for (int f = 4 * lane; f < kb; f += 4 * WAVE) {
+            float v[4] = {0.f, 0.f, 0.f, 0.f};
+            if (ok && (k & 3) == 0 && f < k) {
+                const float4 x = *reinterpret_cast<const float4 *>(P + u * k + f);
+                v[0] = x.x, v[1] = x.y, v[2] = x.z, v[3] = x.w;
+            } else if (ok) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = f + e < k ? P[u * k + f + e] : 0.f;
+            }
+            if (f < kp) *reinterpret_cast<float4 *>(Ug + q * kp + f) = float4{v[0], v[1], v[2], v[3]};
+            if (Ugb) {
+                const uint32_t lo = (uint32_t)to_bf16_rne(v[0]) | (uint32_t)to_bf16_rne(v[1]) << 16;
+                const uint32_t hi = (uint32_t)to_bf16_rne(v[2]) | (uint32_t)to_bf16_rne(v[3]) << 16;
+                *reinterpret_cast<uint2 *>(Ugb + q * kb + f) = uint2{lo, hi};
+            }
+        }
+        if (lane == 0) ub[q] = ok ? mu + bu[u] : __int_as_float(0x7fc00000);
     }
 }
 
@@ -162,18 +177,20 @@ template <int KC, bool BF16>
 struct UserFrag {
     f32x4 f[BF16 ? 1 : KC];
     bf16x8 b[BF16 ? KC : 1];
-    __device__ __forceinline__ void load(const float *Ug, const uint16_t *Ugb, int64_t urow, int kp, int kb, int grp) {
+    // chunks c0 .. c0 + KC - 1 of the row (16 factors each in FP32, 32 in BF16)
+    __device__ __forceinline__ void load(const float *Ug, const uint16_t *Ugb, int64_t urow, int kp, int kb, int grp,
+                                         int c0 = 0) {
         if (!BF16) {
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 f[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-                if (c * 16 < kp) f[c] = *reinterpret_cast<const f32x4 *>(Ug + urow * kp + c * 16 + 4 * grp);
+                if ((c0 + c) * 16 < kp) f[c] = *reinterpret_cast<const f32x4 *>(Ug + urow * kp + (c0 + c) * 16 + 4 * grp);
             }
         } else {
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 uint4 raw = {0u, 0u, 0u, 0u};
-                if (c * 32 < kb) raw = *reinterpret_cast<const uint4 *>(Ugb + urow * kb + c * 32 + 8 * grp);
+                if ((c0 + c) * 32 < kb) raw = *reinterpret_cast<const uint4 *>(Ugb + urow * kb + (c0 + c) * 32 + 8 * grp);
                 b[c] = __builtin_bit_cast(bf16x8, raw);
             }
         }
@@ -188,12 +205,12 @@ struct ItemFrag {
     f32x4 f[BF16 ? 1 : KC];
     uint4 b[BF16 ? KC : 1];
     __device__ __forceinline__ void load(const float *__restrict__ Qf, const uint16_t *__restrict__ Qb, int64_t irow,
-                                         bool irow_ok, int k, int kb, int grp) {
+                                         bool irow_ok, int k, int kb, int grp, int c0 = 0) {
         if (!BF16) {
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 f32x4 a = {0.f, 0.f, 0.f, 0.f};
-                const int f0 = c * 16 + 4 * grp;
+                const int f0 = (c0 + c) * 16 + 4 * grp;
                 if (irow_ok) {
                     if (f0 + 3 < k && (k & 3) == 0) {
                         a = *reinterpret_cast<const f32x4 *>(Qf + irow * k + f0);
@@ -208,7 +225,8 @@ struct ItemFrag {
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 uint4 raw = {0u, 0u, 0u, 0u};
-                if (irow_ok && c * 32 < kb) raw = *reinterpret_cast<const uint4 *>(Qb + irow * kb + c * 32 + 8 * grp);
+                if (irow_ok && (c0 + c) * 32 < kb)
+                    raw = *reinterpret_cast<const uint4 *>(Qb + irow * kb + (c0 + c) * 32 + 8 * grp);
                 b[c] = raw;
             }
         }
@@ -258,14 +276,14 @@ constexpr int SAMPLE_MAX = 1024;
 // Stored as an ordered key; 0 = no threshold (r = 0).  Also clears the
 // user's candidate count.  One workgroup of SMP_WAVES waves per 16-user tile,
 // each wave taking every SMP_WAVES-th sample tile in the sweep; lane (u, g)
-// holds user u's scores.  The BF16 form fits 64 registers (no row prefetch),
-// so two workgroups share a CU and one's selection overlaps the other's
-// sweep.
+// holds user u's scores.  The pass fits 64 registers (no row prefetch;
+// fragments in pieces of up to 4 chunks), so two workgroups share a CU and
+// one's selection overlaps the other's sweep.
 constexpr int SMP_WAVES = 16;
 static_assert(SMP_WAVES == TU, "one wave per user of the tile selects its threshold");
 
 template <int KC, bool BF16>
-__global__ __launch_bounds__(SMP_WAVES *WAVE, BF16 ? 8 : 4) void sample_threshold_kernel(
+__global__ __launch_bounds__(SMP_WAVES *WAVE, 8) void sample_threshold_kernel(
     const float *__restrict__ Ug, const uint16_t *__restrict__ Ugb, const float *__restrict__ Qf,
     const uint16_t *__restrict__ Qb, const float *__restrict__ bi, int64_t n, int k, int kp, int kb, int s, int r,
     uint32_t *__restrict__ thr, uint32_t *__restrict__ cnt) {
@@ -278,8 +296,6 @@ __global__ __launch_bounds__(SMP_WAVES *WAVE, BF16 ? 8 : 4) void sample_threshol
         if (tid < TU) thr[tile * TU + tid] = 0u;
         return;
     }
-    UserFrag<KC, BF16> U;
-    U.load(Ug, Ugb, tile * TU + ucol, kp, kb, grp);
     const int step = SMP_WAVES * TI;
     auto sample_bias = [&](int t0, float (&b)[4]) {
 #pragma unroll
@@ -288,43 +304,28 @@ __global__ __launch_bounds__(SMP_WAVES *WAVE, BF16 ? 8 : 4) void sample_threshol
             b[rr] = t < s ? bi[(int64_t)t * n / s] : 0.f;
         }
     };
-    // the wave's sample tiles, the next tile's rows loaded while the current
-    // one is multiplied
-    if (BF16) {
-        for (int t0 = wave * TI; t0 < s; t0 += step) {
-            ItemFrag<KC, BF16> A;
-            float b[4];
-            const int ta = t0 + ucol;
-            A.load(Qf, Qb, (int64_t)ta * n / s, ta < s, k, kb, grp);
-            sample_bias(t0, b);
-            const f32x4 acc = tile_mma(U, A, f32x4{b[0], b[1], b[2], b[3]});
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int t = t0 + 4 * grp + rr;
-                if (t < s) keys[ucol][t] = float_to_ordered(acc[rr]);
-            }
-        }
-    } else {
-        ItemFrag<KC, BF16> A, An;
-        float b[4], bn[4];
-        int t0 = wave * TI;
+    // the wave's sample tiles; user and item fragments in pieces of H <= 4
+    // chunks (the user's loaded once when there is one piece), multiplied in
+    // the same order as one tile_mma over all KC chunks
+    constexpr int H = KC > 4 ? 4 : KC;
+    UserFrag<H, BF16> U;
+    if (H == KC) U.load(Ug, Ugb, tile * TU + ucol, kp, kb, grp);
+    for (int t0 = wave * TI; t0 < s; t0 += step) {
         const int ta = t0 + ucol;
-        A.load(Qf, Qb, (int64_t)ta * n / s, ta < s, k, kb, grp);
+        float b[4];
         sample_bias(t0, b);
-        for (; t0 < s; t0 += step) {
-            const int tn = t0 + step + ucol;
-            An.load(Qf, Qb, (int64_t)tn * n / s, tn < s, k, kb, grp);
-            sample_bias(t0 + step, bn);
-            // the bias as the accumulator's start, as in the filter
-            const f32x4 acc = tile_mma(U, A, f32x4{b[0], b[1], b[2], b[3]});
+        f32x4 acc = {b[0], b[1], b[2], b[3]};
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int t = t0 + 4 * grp + rr;
-                if (t < s) keys[ucol][t] = float_to_ordered(acc[rr]);
-            }
-            A = An;
+        for (int h = 0; h < KC / H; ++h) {
+            if (H != KC) U.load(Ug, Ugb, tile * TU + ucol, kp, kb, grp, h * H);
+            ItemFrag<H, BF16> A;
+            A.load(Qf, Qb, (int64_t)ta * n / s, ta < s, k, kb, grp, h * H);
+            acc = tile_mma(U, A, acc);
+        }
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) b[rr] = bn[rr];
+        for (int rr = 0; rr < 4; ++rr) {
+            const int t = t0 + 4 * grp + rr;
+            if (t < s) keys[ucol][t] = float_to_ordered(acc[rr]);
         }
     }
     __syncthreads();
@@ -1108,7 +1109,7 @@ TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
 }
 
 void topk_gather(Model &M, const TopkPlan &T, const int32_t *d_users, unsigned char *work, hipStream_t s) {
-    const int grid = (int)std::min<int64_t>((T.nu_pad * T.kb + 255) / 256, 8192);
+    const int grid = (int)std::min<int64_t>((T.nu_pad + 3) / 4, 8192);  // four rows per 256-thread block
     gather_users_kernel<<<grid, 256, 0, s>>>(d_users, T.nu, T.nu_pad, M.m, M.P.as<float>(), M.bu.as<float>(),
                                             (float)M.mu, M.k, T.kp, T.kb, reinterpret_cast<float *>(work + T.off_ug),
                                             T.bf ? reinterpret_cast<uint16_t *>(work + T.off_ugb) : nullptr,

@@ -484,8 +484,10 @@ static int dispatch_kc(int kc) { return kc <= 2 ? kc : kc <= 4 ? 4 : kc <= 8 ? 8
 // largest gives a cut bin; every key in the cut bin and above is kept),
 // sorts those (descending keys) and writes the best `need` (0 = none).  A
 // user with fewer than `need` candidates under a real threshold, with an
-// overflowed buffer, or keeping more than KEEP keys (scores crowded into one
-// bin) is marked in fail[] for the full-selection kernel.  The wave
+// overflowed buffer, or with more than KEEP - need keys whose score ties the
+// need-th best (a cut bin holding too many keys is first narrowed by an
+// exact selection of that score) is marked in fail[] for the full-selection
+// kernel.  The wave
 // reads its candidates from the global buffer once per phase (the reads
 // after the first hit in the caches) and needs no workgroup barrier.
 constexpr int FIN_WG = WAVE;
@@ -518,7 +520,8 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
 
 // The histogram cut of one user's candidates by one wave: every key that
 // can be among the best `need` goes to buf (the first KEEP of them; the
-// return value is the kept count, which may exceed KEEP).  edge_rank gets a
+// return value is the kept count, which exceeds KEEP only when more than
+// KEEP - need keys tie with the need-th best).  edge_rank gets a
 // lower bound on the high half of the key of rank `rank` (<= need): the
 // smallest high half of the bins that hold the best `rank` keys (0 when
 // total <= need and no histogram was made).
@@ -584,6 +587,36 @@ __device__ __forceinline__ int fin_cut(const uint64_t *__restrict__ mine, int to
         if (x < total) {
             key = mine[x];
             keep = bin_of(key) >= cut;
+        }
+        const uint64_t bal = __ballot(keep);
+        const int at = m + __popcll(bal & ((1ull << lane) - 1ull));
+        if (keep && at < KEEP) buf[at] = key;
+        m += __popcll(bal);
+    }
+    if (m <= KEEP) return m;
+    // The cut bin holds too many keys (a few far scores stretch the bins):
+    // the high half of the need-th best key, bit by bit from the top (a bit
+    // stays when at least need keys reach the value with it set), and every
+    // key at or above it -- need plus the keys tied with it.  No rank edge on
+    // this path.
+    uint32_t hq = 0u;
+    for (int bit = 31; bit >= 0; --bit) {
+        const uint32_t c1 = hq | (1u << bit);
+        uint32_t c = 0u;
+        for (int x = lane; x < total; x += WAVE) c += (uint32_t)(mine[x] >> 32) >= c1 ? 1u : 0u;
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) c += (uint32_t)__shfl_xor((int)c, off, WAVE);
+        if (c >= (uint32_t)need) hq = c1;
+    }
+    edge_rank = 0u;
+    m = 0;
+    for (int x0 = 0; x0 < total; x0 += WAVE) {
+        const int x = x0 + lane;
+        uint64_t key = 0ull;
+        bool keep = false;
+        if (x < total) {
+            key = mine[x];
+            keep = (uint32_t)(key >> 32) >= hq;
         }
         const uint64_t bal = __ballot(keep);
         const int at = m + __popcll(bal & ((1ull << lane) - 1ull));

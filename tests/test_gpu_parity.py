@@ -457,6 +457,31 @@ def test_topk_bf16_crowded_scores_take_the_full_selection(B):
         assert np.all(scores == 1.0)
 
 
+def test_topk_outlier_score_narrows_the_cut(B):
+    """One item far above the rest stretches the finish pass's histogram so
+    that its cut bin holds all 700 other candidates (500 tied at the
+    threshold's score, 200 distinct just above), more than it keeps in LDS;
+    the pass then selects the need-th best score exactly and goes on.  Zero
+    user factors make every score its item bias exactly: the answer is the
+    outlier, then the 99 best of the 200, in both precisions."""
+    m, n, k, K = 40, 17800, 128, 100
+    rng = np.random.default_rng(9)
+    Q = rng.normal(0, 0.3, (n, k)).astype(np.float32)
+    bi = np.zeros(n, np.float32)
+    top = rng.choice(n, 701, replace=False)
+    bi[top[1:201]] = (1.0 + 1e-6 * (1 + rng.permutation(200))).astype(np.float32)
+    bi[top[201:]] = 1.0
+    bi[top[0]] = 1000.0
+    G = B.Model(m, n, k, 4)
+    G.set_factors(np.zeros((m, k), np.float32), Q, np.zeros(m, np.float32), bi, 0.0)
+    want = np.lexsort((np.arange(n), -bi.astype(np.float64)))[:K]
+    users = np.arange(m, dtype=np.int32)
+    for fn in (G.topk, G.topk_bf16):
+        items, scores = fn(users, K)
+        assert np.all(items == want[None, :])
+        assert np.array_equal(scores, np.broadcast_to(bi[want], scores.shape))
+
+
 # ---------------------------------------------------------------- fold-in
 @pytest.mark.parametrize("k,nr", [(128, 5), (128, 500), (64, 37), (13, 100), (256, 300), (1000, 60)])
 def test_foldin_matches_oracle(B, orc, k, nr):

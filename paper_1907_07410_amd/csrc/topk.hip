@@ -53,6 +53,7 @@ __device__ __forceinline__ uint16_t to_bf16_rne(float x) {
     b += 0x7fffu + ((b >> 16) & 1u);
     return (uint16_t)(b >> 16);
 }
+__device__ __forceinline__ float bf16_value(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ------------------------------------------------------------ bf16 tables
 __global__ void bf16_table_kernel(const float *__restrict__ A, int64_t rows, int k, int kb, uint16_t *__restrict__ out) {
@@ -64,36 +65,34 @@ __global__ void bf16_table_kernel(const float *__restrict__ A, int64_t rows, int
     }
 }
 
-// Gather the requested users' rows: FP32 (stride kp, zero padded), BF16
-// (stride kb) and the per-user offset mu + bu_u.  Invalid ids get a zero
-// vector and a NaN offset (their rows decode to item -1).
-// Bounds used by the BF16 path's candidate drop: st[0] >= max_j ||Q_j||_2
-// (the FP32 norm inflated by 1e-4 relative, more than its rounding for
-// k <= 256) and st[1] = max_j |bi_j|, as non-negative floats whose bits
-// order like the values.
-__global__ void item_stats_clear_kernel(float *st) {
-    if (threadIdx.x < 2) st[threadIdx.x] = 0.f;
-}
-__global__ void item_stats_kernel(const float *__restrict__ Q, const float *__restrict__ bi, int64_t n, int k,
-                                  float *st) {
-    float qn = 0.f, bm = 0.f;
-    for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-        float s2 = 0.f;
-        for (int f = 0; f < k; ++f) s2 = fmaf(Q[j * k + f], Q[j * k + f], s2);
-        qn = fmaxf(qn, sqrtf(s2) * 1.0001f);
-        bm = fmaxf(bm, fabsf(bi[j]));
-    }
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) {
-        qn = fmaxf(qn, __shfl_xor(qn, off, WAVE));
-        bm = fmaxf(bm, __shfl_xor(bm, off, WAVE));
-    }
-    if (__lane_id() == 0) {
-        atomicMax(reinterpret_cast<unsigned int *>(st), __float_as_uint(qn));
-        atomicMax(reinterpret_cast<unsigned int *>(st) + 1, __float_as_uint(bm));
+// Per-item bounds used by the BF16 path's candidate drop: qn[2 j] >=
+// ||Q_j||_2 and qn[2 j + 1] >= ||bf16(Q_j) - Q_j||_2 (the difference is
+// exact in FP32; both norms inflated by 1e-4 relative, more than their
+// rounding for k <= 256).  One wave per row.
+__global__ void item_norms_kernel(const float *__restrict__ Q, int64_t n, int k, float *__restrict__ qn) {
+    const int lane = threadIdx.x % WAVE;
+    const int64_t w0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) / WAVE;
+    for (int64_t j = w0; j < n; j += nw) {
+        float s2 = 0.f, d2 = 0.f;
+        for (int f = lane; f < k; f += WAVE) {
+            const float v = Q[j * k + f];
+            const float d = bf16_value(to_bf16_rne(v)) - v;
+            s2 = fmaf(v, v, s2);
+            d2 = fmaf(d, d, d2);
+        }
+        s2 = wave_sum_xor(s2);
+        d2 = wave_sum_xor(d2);
+        if (lane == 0) {
+            qn[2 * j] = sqrtf(s2) * 1.0001f;
+            qn[2 * j + 1] = sqrtf(d2) * 1.0001f;
+        }
     }
 }
 
+// Gather the requested users' rows: FP32 (stride kp, zero padded), BF16
+// (stride kb) and the per-user offset mu + bu_u.  Invalid ids get a zero
+// vector and a NaN offset (their rows decode to item -1).
 __global__ void gather_users_kernel(const int32_t *__restrict__ users, int64_t nu, int64_t nu_pad, int64_t m,
                                     const float *__restrict__ P, const float *__restrict__ bu, float mu, int k,
                                     int kp, int kb, float *__restrict__ Ug, uint16_t *__restrict__ Ugb,
@@ -750,17 +749,30 @@ struct RescoreUser {
             }
         }
     }
-    // sum of squares of the row (every lane of a group gets the same value)
-    __device__ __forceinline__ float sq(int k) const {
-        float v = 0.f;
+    // upper bounds on ||p||_2 and ||bf16(p) - p||_2 (every lane of a group
+    // gets the same values; the differences are exact, the norms inflated by
+    // 1e-4 relative)
+    __device__ __forceinline__ void norms(int k, float &pn, float &dp) const {
+        float v = 0.f, w = 0.f;
+        auto add = [&](float x) {
+            const float d = bf16_value(to_bf16_rne(x)) - x;
+            v = fmaf(x, x, v);
+            w = fmaf(d, d, w);
+        };
         if ((k & 3) == 0) {
 #pragma unroll
-            for (int c = 0; c < RS_MAXC; ++c) v += pv[c].x * pv[c].x + pv[c].y * pv[c].y + pv[c].z * pv[c].z + pv[c].w * pv[c].w;
+            for (int c = 0; c < RS_MAXC; ++c) {
+                add(pv[c].x);
+                add(pv[c].y);
+                add(pv[c].z);
+                add(pv[c].w);
+            }
         } else {
 #pragma unroll
-            for (int c = 0; c < 4 * RS_MAXC; ++c) v += ps[c] * ps[c];
+            for (int c = 0; c < 4 * RS_MAXC; ++c) add(ps[c]);
         }
-        return row16_sum(v);
+        pn = sqrtf(row16_sum(v)) * 1.0001f;
+        dp = sqrtf(row16_sum(w)) * 1.0001f;
     }
 };
 
@@ -857,11 +869,19 @@ __global__ __launch_bounds__(64) void rescore_kernel(uint64_t *__restrict__ sel,
 // can still reach the FP32 top K are rescored.  With B a BF16 score (the
 // filter's) and F the FP32 score of the same item, |B - F| <= eps, where eps
 // bounds the rounding of both operands to BF16 (relative 2^-9 each) and the
-// FP32 accumulation in both kernels:
-//   eps = (2^-8 (1.01) + 4 (k + 2) 2^-24) ||p|| max_j ||q_j|| + 4 (k + 2) 2^-24 max_j |b_j|,
-// inflated by 1%.  If T is the K-th best BF16 score among the candidates, K
-// of them have F >= T - eps, so a candidate with B < T - 2 eps has
-// F < T - eps and is not in the FP32 top K of the best Kc; it is dropped.
+// FP32 accumulation in both kernels.  With dp = bf16(p) - p and dq =
+// bf16(q) - q (exact in FP32), the exact BF16 product sum differs from the
+// exact one by p.dq + dp.q + dp.dq, at most ||p|| ||dq|| + ||dp|| ||q|| +
+// ||dp|| ||dq||; each FP32 sum of k + 1 terms (the MFMA's, whatever its
+// order, even truncating, and the rescore's) errs by at most 2 (k + 1) 2^-24
+// times the sum of the magnitudes, bounded through the same norms and |b|:
+//   eps = ||p|| ||dq|| + ||dp|| ||q|| + ||dp|| ||dq||
+//         + 4 (k + 2) 2^-24 ((||p|| + ||dp||)(||q|| + ||dq||) + ||p|| ||q|| + 2 |b|),
+// inflated by 1%, the item terms maximised over the kept keys (which hold
+// the best Kc).
+// If T is the K-th best BF16 score among the candidates, K of them have
+// F >= T - eps, so a kept candidate with B < T - 2 eps has F < T - eps and
+// is not in the FP32 top K of the best Kc; it is dropped.
 // T is bounded below by the lower edge of the histogram bin holding the
 // K-th best key.  The kept keys above that bound form a prefix of the key
 // order; when there are at most Kc of them they are all among the best Kc
@@ -873,7 +893,7 @@ template <int KEEP, int RS_MAXC>
 __global__ __launch_bounds__(FIN_WG) void finish_rescore_kernel(
     const uint32_t *__restrict__ thr, const uint32_t *__restrict__ cnt, const uint64_t *__restrict__ cand, int capg,
     int Kc, int K, const float *__restrict__ Ug, int kp, const float *__restrict__ Qf, const float *__restrict__ bi,
-    int k, const float *__restrict__ stats, int prune, uint32_t *__restrict__ fail, uint64_t *__restrict__ sel) {
+    int k, const float *__restrict__ qn, int prune, uint32_t *__restrict__ fail, uint64_t *__restrict__ sel) {
     __shared__ uint64_t buf[KEEP];
     __shared__ uint32_t hist[FIN_BINS];
     const int lane = threadIdx.x;
@@ -896,8 +916,26 @@ __global__ __launch_bounds__(FIN_WG) void finish_rescore_kernel(
     // the drop bound (no drop without a histogram edge or when turned off)
     float lim = -INFINITY;
     if (prune && edge != 0u) {
+        // the largest item norm, BF16 residual norm and |bias| among the
+        // kept keys
+        float qm = 0.f, dm = 0.f, bm = 0.f;
+        for (int x = lane; x < m; x += WAVE) {
+            const int32_t item = key_item(buf[x]);
+            qm = fmaxf(qm, qn[2 * (int64_t)item]);
+            dm = fmaxf(dm, qn[2 * (int64_t)item + 1]);
+            bm = fmaxf(bm, fabsf(bi[item]));
+        }
+#pragma unroll
+        for (int off = 1; off < WAVE; off <<= 1) {
+            qm = fmaxf(qm, __shfl_xor(qm, off, WAVE));
+            dm = fmaxf(dm, __shfl_xor(dm, off, WAVE));
+            bm = fmaxf(bm, __shfl_xor(bm, off, WAVE));
+        }
+        float pn, dp;
+        P.norms(k, pn, dp);
         const float g = 4.f * (float)(k + 2) * 0x1p-24f;
-        const float eps = 1.01f * ((0x1p-8f * 1.01f + g) * sqrtf(P.sq(k)) * 1.0001f * stats[0] + g * stats[1]) + 1e-30f;
+        const float eps =
+            1.01f * (pn * dm + dp * qm + dp * dm + g * ((pn + dp) * (qm + dm) + pn * qm + 2.f * bm)) + 1e-30f;
         const float t = ordered_to_float(edge);
         lim = t - 2.f * eps - fabsf(t) * 0x1p-20f;
         if (!(lim == lim)) lim = -INFINITY;
@@ -960,7 +998,7 @@ static int cap_for(int K) {
 // Pass kernels of one request for the given latent chunk count KC.
 template <int KC, bool BF16>
 static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ugb, const float *Qf,
-                          const uint16_t *Qb, const float *bi, int64_t n, int k, const float *stats, uint32_t *thr,
+                          const uint16_t *Qb, const float *bi, int64_t n, int k, const float *qn, uint32_t *thr,
                           uint32_t *cnt, uint32_t *fail, uint64_t *cand, uint64_t *sel, hipStream_t s) {
     const unsigned tiles = (unsigned)(T.nu_pad / TU);
     sample_threshold_kernel<KC, BF16><<<tiles, SMP_WAVES * WAVE, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb, T.s, T.r, thr, cnt);
@@ -978,16 +1016,16 @@ static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ug
         const bool k128 = k <= 128;
         if (small && k128)
             finish_rescore_kernel<FIN_KEEP_SMALL, 2><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, T.K, Ug,
-                                                                            T.kp, Qf, bi, k, stats, T.prune, fail, sel);
+                                                                            T.kp, Qf, bi, k, qn, T.prune, fail, sel);
         else if (small)
             finish_rescore_kernel<FIN_KEEP_SMALL, 4><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, T.K, Ug,
-                                                                            T.kp, Qf, bi, k, stats, T.prune, fail, sel);
+                                                                            T.kp, Qf, bi, k, qn, T.prune, fail, sel);
         else if (k128)
             finish_rescore_kernel<FIN_KEEP, 2><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, T.K, Ug, T.kp,
-                                                                      Qf, bi, k, stats, T.prune, fail, sel);
+                                                                      Qf, bi, k, qn, T.prune, fail, sel);
         else
             finish_rescore_kernel<FIN_KEEP, 4><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, T.K, Ug, T.kp,
-                                                                      Qf, bi, k, stats, T.prune, fail, sel);
+                                                                      Qf, bi, k, qn, T.prune, fail, sel);
     } else {
         if (small)
             finish_kernel<FIN_KEEP_SMALL><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, fail, sel);
@@ -1020,16 +1058,16 @@ static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ug
 
 template <bool BF16>
 static void passes_dispatch(int kc, const TopkPlan &T, const float *Ug, const uint16_t *Ugb, const float *Qf,
-                            const uint16_t *Qb, const float *bi, int64_t n, int k, const float *stats, uint32_t *thr,
+                            const uint16_t *Qb, const float *bi, int64_t n, int k, const float *qn, uint32_t *thr,
                             uint32_t *cnt, uint32_t *fail, uint64_t *cand, uint64_t *sel, hipStream_t s) {
     switch (kc) {
-    case 1: launch_passes<1, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, stats, thr, cnt, fail, cand, sel, s); break;
-    case 2: launch_passes<2, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, stats, thr, cnt, fail, cand, sel, s); break;
+    case 1: launch_passes<1, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, qn, thr, cnt, fail, cand, sel, s); break;
+    case 2: launch_passes<2, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, qn, thr, cnt, fail, cand, sel, s); break;
     case 3:
-    case 4: launch_passes<4, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, stats, thr, cnt, fail, cand, sel, s); break;
+    case 4: launch_passes<4, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, qn, thr, cnt, fail, cand, sel, s); break;
     case 5: case 6: case 7:
-    case 8: launch_passes<8, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, stats, thr, cnt, fail, cand, sel, s); break;
-    default: launch_passes<16, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, stats, thr, cnt, fail, cand, sel, s); break;
+    case 8: launch_passes<8, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, qn, thr, cnt, fail, cand, sel, s); break;
+    default: launch_passes<16, BF16>(T, Ug, Ugb, Qf, Qb, bi, n, k, qn, thr, cnt, fail, cand, sel, s); break;
     }
 }
 
@@ -1049,17 +1087,17 @@ static int sample_rank(double lambda, double eps) {
     return r;
 }
 
-// The BF16 item table, followed (at the next 256-byte boundary) by two
-// floats: an upper bound on the item rows' 2-norms and the largest |bias|.
+// The BF16 item table, followed (at the next 256-byte boundary) by 2 n
+// floats: bounds on each item row's 2-norm and on its BF16 residual's.
 static size_t bf16_table_bytes(const Model &M) { return ((size_t)M.n * round_up(M.k, 32) * 2 + 255) & ~size_t(255); }
-static float *bf16_item_stats(Model &M) {
+static float *bf16_item_norms(Model &M) {
     return reinterpret_cast<float *>(M.Qb.as<unsigned char>() + bf16_table_bytes(M));
 }
 
 void ensure_bf16_items(Model &M, bool may_alloc) {
     if (M.bf16_valid) return;
     const int kb = round_up(M.k, 32);
-    const size_t need = bf16_table_bytes(M) + 256;
+    const size_t need = bf16_table_bytes(M) + (((size_t)M.n * 8 + 255) & ~size_t(255));
     if (M.Qb.bytes < need) {
         if (!may_alloc)
             BMF_FAIL(BMF_E_STATE, "the BF16 item table has no device memory yet: run one BF16 top-K call that may "
@@ -1069,11 +1107,8 @@ void ensure_bf16_items(Model &M, bool may_alloc) {
     const int grid = (int)std::min<int64_t>((M.n * kb + 255) / 256, 8192);
     bf16_table_kernel<<<grid, 256, 0, M.stream>>>(M.Q.as<float>(), M.n, M.k, kb, M.Qb.as<uint16_t>());
     BMF_HIP(hipGetLastError());
-    float *st = bf16_item_stats(M);
-    item_stats_clear_kernel<<<1, 64, 0, M.stream>>>(st);
-    BMF_HIP(hipGetLastError());
-    const int sgrid = (int)std::min<int64_t>((M.n + 255) / 256, 4096);
-    item_stats_kernel<<<sgrid, 256, 0, M.stream>>>(M.Q.as<float>(), M.bi.as<float>(), M.n, M.k, st);
+    const int ngrid = (int)std::min<int64_t>((M.n + 3) / 4, 8192);  // four rows per 256-thread block
+    item_norms_kernel<<<ngrid, 256, 0, M.stream>>>(M.Q.as<float>(), M.n, M.k, bf16_item_norms(M));
     BMF_HIP(hipGetLastError());
     M.bf16_valid = true;
 }
@@ -1163,7 +1198,7 @@ void topk_score(Model &M, const TopkPlan &T, unsigned char *work, int32_t *d_ite
     if (T.bf) {
         if (!M.bf16_valid) BMF_FAIL(BMF_E_STATE, "BF16 item table not prepared");
         passes_dispatch<true>(T.kb / 32, T, Ug, Ugb, M.Q.as<float>(), M.Qb.as<uint16_t>(), M.bi.as<float>(), M.n, M.k,
-                              bf16_item_stats(M), thr, cnt, fail, cand, sel, s);
+                              bf16_item_norms(M), thr, cnt, fail, cand, sel, s);
     } else {
         passes_dispatch<false>(T.kp / 16, T, Ug, Ugb, M.Q.as<float>(), nullptr, M.bi.as<float>(), M.n, M.k, nullptr,
                                thr, cnt, fail, cand, sel, s);

@@ -12,18 +12,23 @@
 //  2. filter: the full user x item contraction, split over the item range
 //     across workgroups; every score at or above the user's threshold is
 //     appended to the user's candidate buffer in global memory;
-//  3. finish: one workgroup per user sorts its candidates and keeps the best.
-// A user whose buffer got fewer than the needed candidates (or overflowed)
-// is redone by the full-selection kernel (scores filtered against a running
-// K-th best in an LDS buffer over all items), launched every time and
-// exiting at once when no user of its tile needs it.  The result is exact in
-// both cases: the best items of the candidates are the best items overall
-// whenever enough items reach the threshold.
+//  3. finish: one wave per user keeps the candidates that can be among the
+//     best (a histogram cut), sorts them and keeps the best.
+// A user whose buffer got fewer than the needed candidates (or overflowed,
+// or whose scores tie too often to be cut) is redone by the full-selection
+// kernel (scores filtered against a running K-th best in an LDS buffer over
+// all items), launched every time and exiting at once when no user of its
+// tile needs it.  The result is exact in every case: the best items of the
+// candidates are the best items overall whenever enough items reach the
+// threshold.
 //
 //   FP32 path: v_mfma_f32_16x16x4_f32 on the FP32 factors.
 //   BF16 path: v_mfma_f32_16x16x32_bf16 on round-to-nearest-even BF16
 //              copies (FP32 accumulate) picks Kc candidates, which are then
-//              rescored with FP32 factors and cut to K.
+//              rescored with FP32 factors and cut to K; the finish and the
+//              rescore are one kernel, which rescores only the candidates
+//              that a bound on the BF16 rounding leaves able to reach the
+//              FP32 top K (the answer equals rescoring all Kc).
 //
 // The latent index order inside an MFMA tile is fixed and independent of
 // the users sharing the tile, and a user's threshold and candidates depend

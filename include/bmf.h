@@ -297,8 +297,12 @@ bmf_status bmf_topk(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int
 /* Same ranking with BF16 copies of P and Q on BF16 MFMA (FP32 accumulate)
  * to pick Kc >= K candidates per user, then an FP32 rescore of those
  * candidates (fixed-order FP32 dot products) and a final exact top-K of the
- * rescored values.  The BF16 copies (round to nearest even) are made once
- * after the factors last changed.  Kc = 0 selects K + max(16, K / 2). */
+ * rescored values.  Candidates whose BF16 score lies more than twice a
+ * bound on the BF16 rounding error below the K-th best BF16 score cannot
+ * reach that top K and are not rescored; the answer is the same (setting
+ * BMF_TOPK_PRUNE=0 in the environment turns this off, to check it).  The
+ * BF16 copies (round to nearest even) and per-item norm bounds are made
+ * once after the factors last changed.  Kc = 0 selects K + max(16, K / 2). */
 bmf_status bmf_topk_bf16(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t Kc,
                          int32_t *items_out, float *scores_out);
 

@@ -177,7 +177,8 @@ bmf_status bmf_load_ratings_dev(bmf_ctx *c, const int32_t *u, const int32_t *i, 
  *   p_u  += lr (err q_i - reg p_u);  q_i += lr (err p_u - reg q_i)
  * with p_u and q_i on the right-hand sides taken before the update.
  * Enqueued on the context's stream; returns without waiting.
- * Errors: BMF_E_STATE before a load; BMF_E_DEVICE. */
+ * Errors: BMF_E_STATE before a load (and, with BMF_CHECK_DISJOINT=1, when
+ * the race check of bmf_check_disjoint finds a shared row); BMF_E_DEVICE. */
 bmf_status bmf_epoch(bmf_ctx *c, float lr, float reg);
 
 /* Same with the four (alpha, beta) pairs of Eqs 10-13 given by name:
@@ -289,7 +290,7 @@ bmf_status bmf_loss(bmf_ctx *c, const float hp[8], double *out);
  * fixed accumulation order, so a user's result does not depend on the other
  * users in the call.  items_out[nu*K] (int32), scores_out[nu*K] (float,
  * the predicted rating mu + bu_u + bi_i + p_u . q_i).  If K > n the tail is
- * item -1 / score -inf.  1 <= K <= 1024.
+ * item -1 / score -inf.  1 <= K <= 512.
  * Errors: BMF_E_INVAL, BMF_E_RANGE (user id), BMF_E_DEVICE. */
 bmf_status bmf_topk(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t *items_out,
                     float *scores_out);
@@ -307,7 +308,13 @@ bmf_status bmf_topk_bf16(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K
                          int32_t *items_out, float *scores_out);
 
 /* Device-pointer forms (users, items_out, scores_out on the device);
- * enqueue only. precision: 0 = FP32 MFMA, 1 = BF16 + FP32 rescore. */
+ * enqueue only. precision: 0 = FP32 MFMA, 1 = BF16 + FP32 rescore, 2 =
+ * BF16 only: the K best BF16 scores (BF16 P and Q, FP32 accumulation with
+ * the FP32 item bias as the starting value, ties to the smaller item id),
+ * returned as mu + bu_u plus that score, with no rescore (Kc is not used).
+ * A BF16 score differs from the exact p . q + bi by at most about
+ * 2 * 2^-8 * sum_f |p_f q_f| (two BF16 roundings) plus the FP32 rounding
+ * of the sum, and the ranking follows those scores. */
 bmf_status bmf_topk_dev(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t precision,
                         int32_t Kc, int32_t *items_out, float *scores_out);
 
@@ -319,10 +326,10 @@ bmf_status bmf_topk_dev(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K,
  * runs on until the process ends; no device memory is allocated or freed.
  * A request whose workspace exceeds 64 MiB (at K = 100 about 4,200 users
  * at n = 27,000 and k = 64, about 2,300 at n = 100,000 and k = 128) fails
- * with BMF_E_NOMEM and changes nothing: split it.  precision 1 also needs the
- * BF16 item table's memory, which the first BF16 call that may allocate
- * (bmf_topk_bf16, bmf_topk_dev, bmf_server_create) makes: BMF_E_STATE
- * before that.  Every call on one device shares the array, so calls that
+ * with BMF_E_NOMEM and changes nothing: split it.  Precisions 1 and 2
+ * also need the BF16 item table's memory, which the first BF16 call that
+ * may allocate (bmf_topk_bf16, bmf_topk_dev, bmf_server_create) makes:
+ * BMF_E_STATE before that.  Every call on one device shares the array, so calls that
  * may overlap on one device (other streams, other contexts, other host
  * threads) race and must be serialised by the caller.  Enqueue only. */
 bmf_status bmf_topk_dev_noalloc(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K, int32_t precision,
@@ -494,6 +501,29 @@ bmf_status bmf_chain_depth(int64_t n, const int32_t *u, const int32_t *i, int64_
  * block follow each other, Section 3).  k <= 128.  Errors: BMF_E_INVAL,
  * BMF_E_DEVICE (bmf_last_error(NULL) has the message). */
 bmf_status bmf_debug_chain_floor(int32_t k, int32_t steps, double *ns_per_step);
+
+/* Race check of the schedule on the device (Section 3: the blocks of one
+ * stratum share no user and no item, which is what lets them run at once
+ * without locks).  For each stratum s the check walks the resident records
+ * that the next epoch's SGD kernel reads for the stratum's blocks (the
+ * partition's records, or the LDS-staged kernel's step plan), marks the
+ * user row and the item row each rating updates with a tag of its block,
+ * and counts the ratings that find their row marked by another block of
+ * the same stratum, plus any record naming a row outside its block.
+ * *conflicts is 0 exactly when the blocks of every stratum are disjoint.
+ * pairing: NULL for the schedule the epochs run (stratum s pairs block
+ * column j with block row (j + s) mod b), or a host array of b*b block
+ * rows, pairing[s*b + j] the row that stratum s pairs with column j, to
+ * check another schedule (one that pairs two columns with the same row
+ * shares a user row wherever both of those blocks hold ratings of one
+ * user).  Allocates 8 (m + n) bytes of device memory for the call;
+ * synchronises.  With BMF_CHECK_DISJOINT=1 in the environment, every epoch
+ * on resident ratings runs this check first and, when the count is not 0,
+ * fails with BMF_E_STATE without running.  Errors: BMF_E_INVAL (null
+ * output, pairing entry outside [0, b)), BMF_E_STATE (no ratings loaded,
+ * out-of-core ratings, SGD kernel 2 forced where it does not apply),
+ * BMF_E_DEVICE. */
+bmf_status bmf_check_disjoint(bmf_ctx *c, const int32_t *pairing, int64_t *conflicts);
 
 /* Reduction self-check on the current device: out[0:64], out[64:128],
  * out[128:192] and out[192:256] receive, per lane, the 64-lane sum of

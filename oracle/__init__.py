@@ -5,7 +5,7 @@ this package.  It wraps ``oracle.c`` (plain C, built with gcc into
 ``liboracle.so``) through ctypes; it imports nothing from the HIP library.
 
 What pins each part (tests/test_oracle*.py, CPU): SplitMix64 and the BF16
-rounding against published values; the single-rating update and the bias
+rounding (one value and whole arrays) against published values; the single-rating update and the bias
 dynamics against hand and closed-form values; the partition against an
 independent lexsort; the schedule against the Latin-square property and the
 paper's diagonal-first order; an epoch against the pinned update applied
@@ -80,6 +80,7 @@ def lib():
             L.orc_foldin.argtypes = [C.c_int, p, p, dbl, p, p, i64, C.c_int, p, p, p]
             L.orc_bf16_round.restype = C.c_float
             L.orc_bf16_round.argtypes = [C.c_float]
+            L.orc_bf16_round_n.argtypes = [p, p, i64]
             _lib = L
     return _lib
 
@@ -129,6 +130,14 @@ def schedule(b: int, seed: int, epoch: int, mode: int) -> np.ndarray:
 
 def bf16_round(x: float) -> float:
     return float(lib().orc_bf16_round(C.c_float(x)))
+
+
+def bf16_round_array(x) -> np.ndarray:
+    """bf16_round of every element of an FP32 array (same shape, FP32)."""
+    x = _c(x, np.float32)
+    y = np.empty_like(x)
+    lib().orc_bf16_round_n(_ptr(x), _ptr(y), x.size)
+    return y
 
 
 class Model:

@@ -414,3 +414,9 @@ float orc_bf16_round(float x)
     memcpy(&y, &bits, 4);
     return y;
 }
+
+/* orc_bf16_round over an array: y[t] = orc_bf16_round(x[t]).            */
+void orc_bf16_round_n(const float *x, float *y, int64_t count)
+{
+    for (int64_t t = 0; t < count; ++t) y[t] = orc_bf16_round(x[t]);
+}

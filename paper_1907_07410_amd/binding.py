@@ -66,6 +66,7 @@ def _load():
         "bmf_factor_ptrs": ([p, pp, pp, pp, pp], i32),
         "bmf_rmse": ([p, p, p, p, i64, p], i32),
         "bmf_loss": ([p, p, p], i32),
+        "bmf_check_disjoint": ([p, p, p], i32),
         "bmf_topk": ([p, p, i64, i32, p, p], i32),
         "bmf_topk_bf16": ([p, p, i64, i32, i32, p, p], i32),
         "bmf_topk_dev": ([p, p, i64, i32, i32, i32, p, p], i32),
@@ -281,6 +282,18 @@ class Model:
         hp = _c([lr, reg] * 4 if hp is None else hp, np.float32)
         out = C.c_double()
         self._check(lib.bmf_loss(self._h, _ptr(hp), C.byref(out)))
+        return out.value
+
+    def check_disjoint(self, pairing=None) -> int:
+        """Race check of the strata on the device (bmf_check_disjoint): the
+        count of ratings whose row another block of their stratum touches.
+        pairing: None for the epochs' schedule, else int32 [b, b] block rows
+        (pairing[s, j] = the row stratum s pairs with column j)."""
+        out = C.c_int64()
+        pr = None if pairing is None else _c(pairing, np.int32)
+        if pr is not None and pr.size != self.b * self.b:
+            raise ValueError("pairing must hold b * b block rows")
+        self._check(lib.bmf_check_disjoint(self._h, _ptr(pr), C.byref(out)))
         return out.value
 
     def topk(self, users, K: int):

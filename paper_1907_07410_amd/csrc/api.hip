@@ -526,10 +526,20 @@ bmf_status bmf_loss(bmf_ctx *c, const float hp[8], double *out) {
     });
 }
 
+bmf_status bmf_check_disjoint(bmf_ctx *c, const int32_t *pairing, int64_t *conflicts) {
+    return guarded(c, false, [&] {
+        Model &M = c->M;
+        if (!conflicts) BMF_FAIL(BMF_E_INVAL, "null output");
+        if (!M.loaded) BMF_FAIL(BMF_E_STATE, "no ratings loaded");
+        if (M.ooc.on) BMF_FAIL(BMF_E_STATE, "the race check needs resident ratings");
+        *conflicts = disjoint_check(M, sgd_variant(M), pairing);
+    });
+}
+
 static void check_topk_args(const Model &M, int64_t nu, int32_t K, int32_t precision, int32_t Kc) {
     if (nu < 0) BMF_FAIL(BMF_E_INVAL, "nu < 0");
     if (K < 1 || K > 512) BMF_FAIL(BMF_E_INVAL, "K must be in [1, 512]");
-    if (precision != 0 && precision != 1) BMF_FAIL(BMF_E_INVAL, "precision must be 0 or 1");
+    if (precision < 0 || precision > 2) BMF_FAIL(BMF_E_INVAL, "precision must be 0, 1 or 2");
     if (precision == 1 && Kc != 0 && (Kc < K || Kc > 1008)) BMF_FAIL(BMF_E_INVAL, "Kc must be 0 or in [K, 1008]");
     if (M.k > 256) BMF_FAIL(BMF_E_INVAL, "top-K scoring supports k <= 256");
 }

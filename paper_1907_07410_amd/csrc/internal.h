@@ -254,6 +254,18 @@ void ensure_plan(Model &M);
 
 // SGD: run one epoch of strata in `order`.
 void sgd_epoch(Model &M, const int32_t *order, const HP &hp);
+// The SGD kernel an epoch of M would run (1 or 2; builds the plan when it
+// picks 2).
+int sgd_variant(Model &M);
+// Race check of the resident ratings' strata for SGD kernel `variant`:
+// stratum s pairs column j with block row pairing[s * b + j] (host array;
+// nullptr: (j + s) mod b).  Returns the count of ratings whose user or item
+// row another block of their stratum also touches, or that name a row
+// outside their block (synchronises).
+int64_t disjoint_check(Model &M, int variant, const int32_t *pairing);
+// BMF_CHECK_DISJOINT=1 in the environment: every resident epoch runs the
+// race check first.
+bool disjoint_check_env();
 // Where one stratum's work is: records (reference kernels) or steps
 // (planned kernel), and its block table, indexed br * row_stride + j.
 struct StratumData {
@@ -291,6 +303,9 @@ struct TopkPlan {
     int64_t nu = 0, nu_pad = 0;
     int K = 0, Ksel = 0, kp = 0, kb = 0;
     bool bf = false;
+    // BF16: rescore the candidates in FP32 (precision 1); without it
+    // (precision 2) the answer is the BF16 top K with its BF16 scores
+    bool rescore = false;
     // BF16: drop candidates that provably cannot reach the FP32 top K before
     // rescoring (on unless BMF_TOPK_PRUNE=0 is in the environment)
     int prune = 1;

@@ -575,7 +575,7 @@ static void graph_epoch(Model &M, const int32_t *order, const HP &hp, int varian
     BMF_HIP(hipGraphLaunch(E.exec, M.stream));
 }
 
-void sgd_epoch(Model &M, const int32_t *order, const HP &hp) {
+int sgd_variant(Model &M) {
     int variant = M.sgd_kernel;
     if (M.ooc.on) {
         if (variant == 0) variant = M.ooc.variant;
@@ -588,6 +588,17 @@ void sgd_epoch(Model &M, const int32_t *order, const HP &hp) {
     if (variant == 2 && !M.plan.ok)
         BMF_FAIL(BMF_E_STATE, "the LDS-staged SGD kernel needs k <= 128 and an item slice that leaves room for "
                               "user slots in LDS; use SGD kernel 1 or a larger b");
+    return variant;
+}
+
+void sgd_epoch(Model &M, const int32_t *order, const HP &hp) {
+    const int variant = sgd_variant(M);
+    if (!M.ooc.on && disjoint_check_env()) {
+        const int64_t bad = disjoint_check(M, variant, nullptr);
+        if (bad)
+            BMF_FAIL(BMF_E_STATE, "race check: " + std::to_string(bad) +
+                                      " ratings share a row with another block of their stratum");
+    }
     hipEvent_t ev0 = take_event(M), ev1 = take_event(M);
     BMF_HIP(hipEventRecord(ev0, M.stream));
     if (M.ooc.on) {

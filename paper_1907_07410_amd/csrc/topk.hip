@@ -1017,7 +1017,7 @@ static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ug
     BMF_HIP(hipGetLastError());
     const unsigned rows = (unsigned)T.nu_pad;
     const bool small = T.Ksel <= FIN_KEEP_SMALL_NEED;
-    if (BF16) {
+    if (BF16 && T.rescore) {
         const bool k128 = k <= 128;
         if (small && k128)
             finish_rescore_kernel<FIN_KEEP_SMALL, 2><<<rows, FIN_WG, 0, s>>>(thr, cnt, cand, T.capg, T.Ksel, T.K, Ug,
@@ -1051,7 +1051,7 @@ static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ug
         break;
     }
     BMF_HIP(hipGetLastError());
-    if (BF16) {
+    if (BF16 && T.rescore) {
         // the users the full selection redid
         if (k <= 128)
             rescore_kernel<2><<<(unsigned)T.nu, 64, 0, s>>>(sel, T.Ksel, T.K, fail, Ug, T.kp, Qf, bi, k);
@@ -1106,7 +1106,7 @@ void ensure_bf16_items(Model &M, bool may_alloc) {
     if (M.Qb.bytes < need) {
         if (!may_alloc)
             BMF_FAIL(BMF_E_STATE, "the BF16 item table has no device memory yet: run one BF16 top-K call that may "
-                                  "allocate (bmf_topk_bf16 or bmf_topk_dev with precision 1) first");
+                                  "allocate (bmf_topk_bf16, or bmf_topk_dev with precision 1 or 2) first");
         M.Qb.alloc(need);
     }
     const int grid = (int)std::min<int64_t>((M.n * kb + 255) / 256, 8192);
@@ -1122,8 +1122,9 @@ TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
     TopkPlan T;
     T.nu = nu;
     T.K = K;
-    T.bf = precision == 1;
-    T.Ksel = T.bf ? topk_candidates(K, Kc) : K;
+    T.bf = precision == 1 || precision == 2;
+    T.rescore = precision == 1;
+    T.Ksel = T.rescore ? topk_candidates(K, Kc) : K;
     {
         const char *e = std::getenv("BMF_TOPK_PRUNE");
         T.prune = (e && e[0] == '0' && e[1] == 0) ? 0 : 1;

@@ -412,6 +412,58 @@ def test_topk_bf16_recall_and_rescore(B, orc, k):
     eps_valid(bi_, bs, P, Q, bu, bi, 3.5, users, K, (k + 8) * 2.0 ** -23)
 
 
+@pytest.mark.parametrize("k,n,nu,K", [(128, 17800, 64, 100), (13, 3000, 40, 50), (256, 6000, 17, 100),
+                                      (64, 27000, 33, 300)])
+def test_topk_bf16_only_scores_within_the_rounding_bound(B, orc, k, n, nu, K):
+    """Precision 2 returns the BF16 ranking with its BF16 scores, before any
+    rescore.  Against the oracle on the BF16-rounded tables (products of
+    BF16 values are exact in FP64) the answer is valid to the FP32
+    accumulation bound alone; against the exact FP32-factor scores every
+    returned score lies within 2 * 2^-8 * sum_f |p_f q_f| (each factor
+    rounded once to BF16, unit roundoff 2^-8; the product term 2^-16 is
+    added) plus that accumulation bound, and the set is valid to twice it."""
+    import torch
+    rng = np.random.default_rng(k * 7 + n)
+    m = 200
+    P = rng.normal(0, 0.3, (m, k)).astype(np.float32)
+    Q = rng.normal(0, 0.3, (n, k)).astype(np.float32)
+    bu = rng.normal(0, 0.3, m).astype(np.float32)
+    bi = rng.normal(0, 0.3, n).astype(np.float32)
+    mu = 3.5
+    G = B.Model(m, n, k, 4)
+    G.set_factors(P, Q, bu, bi, mu)
+    users = rng.integers(0, m, nu).astype(np.int32)
+    du = torch.from_numpy(users).cuda()
+    it = torch.full((nu, K), -7, dtype=torch.int32, device="cuda")
+    sc = torch.zeros((nu, K), dtype=torch.float32, device="cuda")
+    G.topk_dev(du, K, 2, 0, it, sc)
+    G.synchronize()
+    items, scores = it.cpu().numpy(), sc.cpu().numpy()
+    acc = (k + 8) * 2.0 ** -23
+    Pb, Qb = orc.bf16_round_array(P), orc.bf16_round_array(Q)
+    # the BF16 ranking: valid to the FP32 accumulation bound of the BF16 sums
+    eps_valid(items, scores, Pb, Qb, bu, bi, mu, users, K, acc)
+    # the rounding bound against the exact scores, score by score
+    Pd, Qd = P.astype(np.float64), Q.astype(np.float64)
+    worst = 0.0
+    for row, u in enumerate(users):
+        s = mu + bu[u] + bi.astype(np.float64) + Qd @ Pd[u]
+        absdot = np.abs(Qd * Pd[u]).sum(axis=1)
+        mag = np.abs(Qb.astype(np.float64) * Pb[u]).sum(axis=1) + np.abs(bi) + abs(mu + bu[u])
+        bound = (2 * 2.0 ** -8 + 2.0 ** -16) * absdot + acc * mag
+        it_ = items[row]
+        err = np.abs(scores[row].astype(np.float64) - s[it_])
+        assert np.all(err <= bound[it_]), (row, (err - bound[it_]).max())
+        worst = max(worst, float((err / bound[it_]).max()))
+        kth = np.sort(s)[::-1][K - 1]
+        assert np.all(s[it_] >= kth - 2 * bound.max()), row
+    log("bf16-only worst error / bound", worst)
+    fi, _ = G.topk(users, K)
+    recall = np.mean([len(set(a) & set(b)) / K for a, b in zip(fi, items)])
+    log("bf16-only recall vs fp32", recall)
+    G.close()
+
+
 @pytest.mark.parametrize("scale,k,Kc", [(0.02, 128, 0), (0.3, 128, 0), (0.05, 64, 300), (0.02, 13, 0)])
 def test_topk_bf16_candidate_drop_changes_nothing(B, monkeypatch, scale, k, Kc):
     """The BF16 path drops candidates whose BF16 score lies more than twice

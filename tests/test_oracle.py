@@ -45,6 +45,22 @@ def test_bf16_rounding_cases(orc):
         assert orc.bf16_round(c["x"]) == c["bf16"], c
 
 
+def test_bf16_rounding_of_arrays(orc):
+    cases = _gold("bf16_rne.json")["cases"]
+    x = np.array([c["x"] for c in cases], dtype=np.float32).reshape(1, -1)
+    y = orc.bf16_round_array(x)
+    assert y.shape == x.shape and y.dtype == np.float32
+    assert [float(v) for v in y[0]] == [c["bf16"] for c in cases]
+    # every element as the one-value form rounds it; a BF16 value has at
+    # most 8 significant bits and lies within half a BF16 step (2^-8
+    # relative) of the input
+    r = np.random.default_rng(5).normal(0, 3, (7, 33)).astype(np.float32)
+    y = orc.bf16_round_array(r)
+    assert all(y.flat[t] == orc.bf16_round(float(r.flat[t])) for t in range(r.size))
+    assert np.all(y.view(np.uint32) & 0xFFFF == 0)
+    assert np.all(np.abs(y.astype(np.float64) - r) <= 2.0 ** -8 * np.abs(r.astype(np.float64)))
+
+
 # ------------------------------------------------------------ update rules
 def _single(orc, g, form):
     inp = g["inputs"]

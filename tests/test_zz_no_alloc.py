@@ -1,5 +1,5 @@
 """The no-allocation top-K entry point (bmf_topk_dev_noalloc) against
-bmf_topk_dev: the same items and scores bit for bit, in both precisions,
+bmf_topk_dev: the same items and scores bit for bit, in all three precisions,
 on two calls in a row (the second with fewer users, so it runs over what
 the first left in the fixed workspace), through the C ABI; oversized
 requests and a missing BF16 table are refused without running anything."""
@@ -35,7 +35,7 @@ def test_noalloc_topk_equals_topk_dev():
     with pytest.raises(B.BmfError) as ex:
         G.topk_dev_noalloc(big, K, 0, 0, it0, sc0)
     assert ex.value.status == B.BMF_E_NOMEM
-    for precision in (0, 1):
+    for precision in (0, 1, 2):
         for nu in (1500, 37):  # the second call is smaller than the first
             log("precision", precision, "users", nu)
             users = torch.from_numpy(rng.integers(0, m, nu).astype(np.int32)).cuda()

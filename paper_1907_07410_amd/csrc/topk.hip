@@ -359,25 +359,46 @@ __global__ __launch_bounds__(SMP_WAVES *WAVE, 8) void sample_threshold_kernel(
 // varying fastest); a wave holds the user fragments of its UT tiles, so each
 // item tile it loads feeds UT tile products (UT times fewer item-table reads
 // than one tile per wave).  Tiles at or beyond `tiles` are skipped.
-// Candidates gather in LDS (FLT_LDS per user, each the score and the item's
-// offset in the split, positions from LDS atomics).  A tile adds at most 16 to a user's
-// list, so when some list holds more than FLT_LDS - 16 after a tile, the
-// wave moves every non-empty list to the global buffer (one counter
-// reservation per user, all users' reservations issued together); the rest
-// goes there at the end.
-constexpr int FLT_LDS = 32;
+// Candidates gather in LDS in per-lane lists: a lane holds four scores of
+// one user per tile product (items 4 grp .. 4 grp + 3 of the tile, user
+// ucol), and appends each one that reaches the user's threshold to its own
+// list for that user tile, FLT_SUB entries of {score, item offset in the
+// split}, with the list length in a register.  Every score is written at
+// the list's end and only a passing one moves the end, so the append takes
+// no branch and no atomic.  Entry e of lane l in list q sits at
+// (q FLT_SUB + e) WAVE + l: a wave's writes at any mix of list lengths
+// fall in distinct banks.  A tile adds at most 4 to a list, so when some
+// list of a user tile holds more than FLT_SUB - 4 after a tile, the four
+// lists of each of that tile's users go to the global buffer (one counter
+// reservation per user); the rest goes there at the end.
+constexpr int FLT_LIST_BYTES = 18 * 1024;  // per workgroup; two per SIMD fit in LDS
+template <int UT>
+constexpr int filter_sub() {
+    return FLT_LIST_BYTES / (UT * WAVE * 8);
+}
 
-template <int KC, bool BF16, int UT>
+// Raw buffer resource over `bytes` bytes from `base`: a load at an offset
+// at or past `bytes` returns zeros and touches no memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+// FAST: the item rows are whole 16-byte chunks (BF16 rows padded to kb, or
+// FP32 rows with k = 16 KC), read through a buffer resource clipped to the
+// split's rows, so a tile's loads need no per-lane address arithmetic and
+// no bounds branch; otherwise plain loads with bounds tests.
+template <int KC, bool BF16, int UT, bool FAST>
 __global__ __launch_bounds__(64, 2) void filter_kernel(const float *__restrict__ Ug, const uint16_t *__restrict__ Ugb,
                                                     const float *__restrict__ Qf, const uint16_t *__restrict__ Qb,
                                                     const float *__restrict__ bi, int64_t n, int k, int kp, int kb,
                                                     int64_t tiles, int64_t per_split, int splits,
                                                     const uint32_t *__restrict__ thr, uint32_t *__restrict__ cnt,
                                                     int capg, uint64_t *__restrict__ cand) {
-    // a list entry: the score and the item's offset in the split (6 bytes)
-    __shared__ float lsc[UT * TU][FLT_LDS];
-    __shared__ uint16_t lit[UT * TU][FLT_LDS];
-    __shared__ uint32_t lcnt[UT * TU];
+    constexpr int SUB = filter_sub<UT>();
+    static_assert(SUB >= 8, "lists too short for the LDS budget");
+    // scores in the first half, item offsets in the second
+    constexpr int HALF = UT * SUB * WAVE;
+    __shared__ uint32_t lst[2 * HALF];
     const int lane = threadIdx.x;
     // the item split varies fastest with the workgroup id: workgroups are
     // dealt to the XCDs in turn, so with a multiple of 8 splits each XCD's L2
@@ -387,96 +408,154 @@ __global__ __launch_bounds__(64, 2) void filter_kernel(const float *__restrict__
     const int64_t iend = std::min<int64_t>(n, ibeg + per_split);
     const int ucol = lane % 16, grp = lane / 16;
     const int nt = (int)std::min<int64_t>(UT, tiles - tile0);  // wave-uniform
-    for (int x = lane; x < UT * TU; x += WAVE) lcnt[x] = 0u;
     UserFrag<KC, BF16> U[UT];
     // thresholds as floats: sv >= tf passes every score whose ordered key
     // reaches the threshold (and, at most, a -0 against a +0 threshold too);
     // no threshold (0) passes every number, and a NaN (an item beyond the
-    // range) nothing
+    // range) nothing.  A user tile beyond the last gets a NaN threshold: its
+    // scores (those of tile 0 again) pass nothing, so its lists stay empty
+    // and the loop needs no test for it.
     float tf[UT];
+    // the end of this lane's list of each user tile, as an index into lst
+    int end[UT];
 #pragma unroll
     for (int q = 0; q < UT; ++q) {
         const int64_t urow = (tile0 + (q < nt ? q : 0)) * TU + ucol;
         U[q].load(Ug, Ugb, urow, kp, kb, grp);
         const uint32_t t = thr[urow];
-        tf[q] = t == 0u ? -INFINITY : ordered_to_float(t);
+        tf[q] = q >= nt ? __builtin_nanf("") : t == 0u ? -INFINITY : ordered_to_float(t);
+        end[q] = q * SUB * WAVE + lane;
     }
-    __syncthreads();
-    // item biases of this lane's four score items of a tile (items
-    // 4 grp .. 4 grp + 3, 16-byte aligned): one load on a whole tile, NaN
-    // beyond the range
-    auto load_bias = [&](int64_t ib, f32x4 &b) {
-        const int64_t item = ib + 4 * grp;
-        if (ib + TI <= iend) {
-            b = *reinterpret_cast<const f32x4 *>(bi + item);
-        } else {
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) b[rr] = item + rr < iend ? bi[item + rr] : __builtin_nanf("");
-        }
-    };
-    // lists to the global buffer: lane x reserves room for user x's list
-    // (one returning atomic per user, all in flight together), then the lanes
-    // copy each list (at most FLT_LDS keys) and empty it.  One wave per
-    // workgroup: its LDS accesses happen in program order.
-    static_assert(UT * TU <= WAVE && FLT_LDS <= WAVE, "one lane per user and per list entry");
-    auto flush = [&]() {
-        const bool own = lane < nt * TU;
-        const uint32_t c = own ? lcnt[lane] : 0u;
+    // user tile q's lists to the global buffer: the four lanes of a user
+    // (ucol + 16 g) add up their lengths, the first reserves the total with
+    // one returning atomic, and each copies its list behind the lists of
+    // the lanes before it.  One wave per workgroup: its LDS accesses happen
+    // in program order.
+    auto flush = [&](int q) {
+        const int first = q * SUB * WAVE + lane;
+        const int c = (end[q] - first) / WAVE;
+        const int c_pair = __shfl_xor(c, 16);
+        const int s2 = c + c_pair;
+        const int s2_other = __shfl_xor(s2, 32);
+        const int total = s2 + s2_other;
+        const int before = ((grp & 1) ? c_pair : 0) + ((grp & 2) ? s2_other : 0);
+        const int64_t urow = (tile0 + q) * TU + ucol;
         uint32_t g = 0u;
-        if (c) g = atomicAdd(&cnt[(tile0 * TU + lane)], c);
-        uint64_t users = __ballot(c != 0u);
-        while (users) {
-            const int x = __builtin_ctzll(users);
-            users &= users - 1;
-            const uint32_t cx = __shfl(c, x), gx = __shfl(g, x);
-            const int64_t urow = tile0 * TU + x;
-            if ((uint32_t)lane < cx && gx + lane < (uint32_t)capg)
-                cand[urow * capg + gx + lane] = rank_key(lsc[x][lane], (int32_t)(ibeg + lit[x][lane]));
+        if (grp == 0 && total > 0) g = atomicAdd(&cnt[urow], (uint32_t)total);
+        g = __shfl(g, ucol);
+        for (int e = 0; e < c; ++e) {
+            const uint32_t at = g + (uint32_t)(before + e);
+            if (at < (uint32_t)capg)
+                cand[urow * capg + at] =
+                    rank_key(__uint_as_float(lst[first + e * WAVE]), (int32_t)(ibeg + lst[HALF + first + e * WAVE]));
         }
-        if (c) lcnt[lane] = 0u;
+        end[q] = first;
     };
-    ItemFrag<KC, BF16> A, An;
-    f32x4 b, bn;
-    A.load(Qf, Qb, ibeg + ucol, ibeg + ucol < iend, k, kb, grp);
-    load_bias(ibeg, b);
-    bn = b;
-    for (int64_t ib = ibeg; ib < iend; ib += TI) {
-        // the next tile's rows and biases, loaded while this one is multiplied
-        const int64_t inext = ib + TI + ucol;
-        An.load(Qf, Qb, inext, inext < iend, k, kb, grp);
-        if (ib + TI < iend) load_bias(ib + TI, bn);
-        // scores with the item bias as the accumulator's start
+    // one tile's scores: with the item bias as the accumulator's start; every
+    // score is written at its list's end and only a passing one moves the
+    // end; then the lists that a further tile could overflow are flushed
+    auto tile = [&](int64_t ib, const ItemFrag<KC, BF16> &A, const f32x4 &b) {
         f32x4 acc[UT];
 #pragma unroll
         for (int q = 0; q < UT; ++q) acc[q] = tile_mma(U[q], A, b);
-        A = An;
+        if (FAST && ib + TI > iend) {
+            // rows past the split read as zeros: no score there
+            const int64_t left = iend - ib;
+#pragma unroll
+            for (int q = 0; q < UT; ++q)
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+                    if (4 * grp + rr >= left) acc[q][rr] = __builtin_nanf("");
+        }
+        const uint32_t off = (uint32_t)(ib - ibeg) + 4u * (uint32_t)grp;
+        bool full = false;
 #pragma unroll
         for (int q = 0; q < UT; ++q) {
-            if (q >= nt) continue;
-            uint32_t pass = 0u;
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) pass |= acc[q][rr] >= tf[q] ? 1u << rr : 0u;
-            if (pass) {
-                const uint32_t base = atomicAdd(&lcnt[q * TU + ucol], (uint32_t)__popc(pass));
-#pragma unroll
-                for (int rr = 0; rr < 4; ++rr) {
-                    const uint32_t pos = base + (uint32_t)__popc(pass & ((1u << rr) - 1u));
-                    if ((pass >> rr & 1u) && pos < (uint32_t)FLT_LDS) {
-                        lsc[q * TU + ucol][pos] = acc[q][rr];
-                        lit[q * TU + ucol][pos] = (uint16_t)(ib - ibeg + 4 * grp + rr);
-                    }
-                }
+            for (int rr = 0; rr < 4; ++rr) {
+                const int e = end[q];
+                lst[e] = __float_as_uint(acc[q][rr]);
+                lst[HALF + e] = off + (uint32_t)rr;
+                end[q] = e + (acc[q][rr] >= tf[q] ? WAVE : 0);
             }
+            full |= end[q] > (q * SUB + SUB - 4) * WAVE + lane;
         }
-        b = bn;
-        if (__ballot(lane < nt * TU && lcnt[lane] > (uint32_t)(FLT_LDS - 16))) flush();
+        if (__ballot(full)) {
+#pragma unroll
+            for (int q = 0; q < UT; ++q)
+                if (__ballot(end[q] > (q * SUB + SUB - 4) * WAVE + lane)) flush(q);
+        }
+    };
+    if constexpr (FAST) {
+        // this lane's 16 bytes of chunk c of its tile row (row ucol, bytes
+        // 16 grp of the chunk's 64): the same offsets in FP32 and in BF16
+        const unsigned char *qb = BF16 ? reinterpret_cast<const unsigned char *>(Qb)
+                                       : reinterpret_cast<const unsigned char *>(Qf);
+        const uint32_t rowb = BF16 ? (uint32_t)kb * 2u : (uint32_t)k * 4u;
+        const uint32_t lq = (uint32_t)ucol * rowb + 16u * (uint32_t)grp;
+        auto load = [&](int64_t ib, ItemFrag<KC, BF16> &A, f32x4 &b) {
+            const int64_t at = std::min<int64_t>(ib, iend);
+            const uint32_t rows = (uint32_t)std::min<int64_t>(iend - at, TI);
+            const __amdgpu_buffer_rsrc_t rq = raw_rsrc(qb + at * rowb, rows * rowb);
+            const __amdgpu_buffer_rsrc_t rb = raw_rsrc(bi + at, rows * 4u);
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                const auto raw = __builtin_amdgcn_raw_buffer_load_b128(rq, lq + 64u * (uint32_t)c, 0, 0);
+                if (BF16)
+                    A.b[c] = __builtin_bit_cast(uint4, raw);
+                else
+                    A.f[c] = __builtin_bit_cast(f32x4, raw);
+            }
+            b = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rb, 16u * (uint32_t)grp, 0, 0));
+        };
+        // two tiles per trip, each loaded one tile ahead into the buffer the
+        // other does not use
+        ItemFrag<KC, BF16> A0, A1;
+        f32x4 b0, b1;
+        load(ibeg, A0, b0);
+        for (int64_t ib = ibeg;;) {
+            load(ib + TI, A1, b1);
+            tile(ib, A0, b0);
+            ib += TI;
+            if (ib >= iend) break;
+            load(ib + TI, A0, b0);
+            tile(ib, A1, b1);
+            ib += TI;
+            if (ib >= iend) break;
+        }
+    } else {
+        // item biases of this lane's four score items of a tile (items
+        // 4 grp .. 4 grp + 3, 16-byte aligned): one load on a whole tile, NaN
+        // beyond the range
+        auto load_bias = [&](int64_t ib, f32x4 &b) {
+            const int64_t item = ib + 4 * grp;
+            if (ib + TI <= iend) {
+                b = *reinterpret_cast<const f32x4 *>(bi + item);
+            } else {
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) b[rr] = item + rr < iend ? bi[item + rr] : __builtin_nanf("");
+            }
+        };
+        ItemFrag<KC, BF16> A, An;
+        f32x4 b, bn;
+        A.load(Qf, Qb, ibeg + ucol, ibeg + ucol < iend, k, kb, grp);
+        load_bias(ibeg, b);
+        bn = b;
+        for (int64_t ib = ibeg; ib < iend; ib += TI) {
+            // the next tile's rows and biases, loaded while this one is multiplied
+            const int64_t inext = ib + TI + ucol;
+            An.load(Qf, Qb, inext, inext < iend, k, kb, grp);
+            if (ib + TI < iend) load_bias(ib + TI, bn);
+            tile(ib, A, b);
+            A = An;
+            b = bn;
+        }
     }
-    flush();
+#pragma unroll
+    for (int q = 0; q < UT; ++q)
+        if (q < nt) flush(q);
 }
 
-// User tiles per filter wave, as measured: two at k <= 64, four at
-// 64 < k <= 128 (FP32 8 chunks, BF16 4), fewer where the user fragments
-// would not fit the registers.
 static constexpr int filter_tiles_per_wave(int kc, bool bf16) {
     return bf16 ? (kc == 4 ? 4 : kc <= 8 ? 2 : 1) : (kc == 8 ? 4 : kc <= 4 ? 2 : 1);
 }
@@ -1011,9 +1090,12 @@ static void launch_passes(const TopkPlan &T, const float *Ug, const uint16_t *Ug
     constexpr int UT = filter_tiles_per_wave(KC, BF16);
     if (T.ut != UT) BMF_FAIL(BMF_E_STATE, "top-K plan made for another filter shape");
     const unsigned groups = (unsigned)((tiles + UT - 1) / UT);
-    filter_kernel<KC, BF16, UT><<<groups * (unsigned)T.S, 64, 0, s>>>(Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb,
-                                                                     (int64_t)tiles, T.per_split, T.S, thr, cnt,
-                                                                     T.capg, cand);
+    if (BF16 || k == 16 * KC)
+        filter_kernel<KC, BF16, UT, true><<<groups * (unsigned)T.S, 64, 0, s>>>(
+            Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb, (int64_t)tiles, T.per_split, T.S, thr, cnt, T.capg, cand);
+    else
+        filter_kernel<KC, BF16, UT, false><<<groups * (unsigned)T.S, 64, 0, s>>>(
+            Ug, Ugb, Qf, Qb, bi, n, k, T.kp, T.kb, (int64_t)tiles, T.per_split, T.S, thr, cnt, T.capg, cand);
     BMF_HIP(hipGetLastError());
     const unsigned rows = (unsigned)T.nu_pad;
     const bool small = T.Ksel <= FIN_KEEP_SMALL_NEED;

@@ -259,6 +259,22 @@ __device__ __forceinline__ f32x4 tile_mma(const UserFrag<KC, BF16> &U, const Ite
     return acc;
 }
 
+// Chunk c of tile_mma alone (16 factors in FP32: four MFMAs; 32 in BF16:
+// one): tile_mma is these for c = 0 .. KC - 1 in turn.
+template <int KC, bool BF16>
+__device__ __forceinline__ f32x4 tile_mma_chunk(const UserFrag<KC, BF16> &U, const ItemFrag<KC, BF16> &A, int c,
+                                                f32x4 acc) {
+    if (!BF16) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A.f[c][0], U.f[c][0], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A.f[c][1], U.f[c][1], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A.f[c][2], U.f[c][2], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A.f[c][3], U.f[c][3], acc, 0, 0, 0);
+    } else {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, A.b[c]), U.b[c], acc, 0, 0, 0);
+    }
+    return acc;
+}
+
 template <int KC, bool BF16>
 __device__ __forceinline__ f32x4 tile_dots(const UserFrag<KC, BF16> &U, const float *__restrict__ Qf,
                                            const uint16_t *__restrict__ Qb, int64_t irow, bool irow_ok, int k,
@@ -270,11 +286,26 @@ __device__ __forceinline__ f32x4 tile_dots(const UserFrag<KC, BF16> &U, const fl
 
 constexpr int SAMPLE_MAX = 1024;
 
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, WAVE));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, WAVE));
+    return v;
+}
+
 // Pass 1: threshold per user: the r-th best of its scores over the sample
-// items t * n / s, t < s (so at least r sampled items reach it).  One sweep
-// stores the sampled scores of the tile's 16 users in LDS as ordered keys;
-// then wave w finds user w's r-th largest key bit by bit, from the top: a bit
-// is kept when at least r keys reach the value with it set.  The filter
+// items t * n / s, t < s, rounded down (so at least r sampled items reach
+// it).  One sweep stores the sampled scores of the tile's 16 users in LDS as
+// ordered keys; then wave w finds user w's r-th largest key bit by bit, from
+// the top: a bit is kept when at least r keys reach the value with it set.
+// The bits above the highest one in which the smallest and the largest key
+// differ are those two keys' common bits, and the search stops above the
+// lowest SMP_LOW_BITS bits (left zero: the threshold is at most 2^-15 of its
+// value below the exact r-th key, so it admits a few more items).  The filter
 // scores a sampled item exactly as this pass does (the same MFMA tile and
 // bias), so the r sampled items at or above the threshold pass it there too.
 // Stored as an ordered key; 0 = no threshold (r = 0).  Also clears the
@@ -284,6 +315,7 @@ constexpr int SAMPLE_MAX = 1024;
 // fragments in pieces of up to 4 chunks), so two workgroups share a CU and
 // one's selection overlaps the other's sweep.
 constexpr int SMP_WAVES = 16;
+constexpr int SMP_LOW_BITS = 8;
 static_assert(SMP_WAVES == TU, "one wave per user of the tile selects its threshold");
 
 template <int KC, bool BF16>
@@ -342,14 +374,27 @@ __global__ __launch_bounds__(SMP_WAVES *WAVE, 8) void sample_threshold_kernel(
         const int t = lane + WAVE * j;
         kv[j] = t < s ? mine[t] : 0u;  // 0: below every real key, never counted
     }
-    uint32_t ans = 0u;
-    for (int bit = 31; bit >= 0; --bit) {
+    uint32_t lo = ~0u, hi = 0u;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        if (lane + WAVE * j < s) lo = min(lo, kv[j]);
+        hi = max(hi, kv[j]);
+    }
+    lo = wave_min_u32(lo);
+    hi = wave_max_u32(hi);
+    // every key lies in [lo, hi], so the r-th largest shares their common
+    // high bits; the search sets the rest from the highest differing bit
+    const uint32_t diff = lo ^ hi;
+    const int top = diff ? 31 - __builtin_clz(diff) : SMP_LOW_BITS - 1;
+    uint32_t ans = top >= 31 ? 0u : hi & ~((2u << top) - 1u);
+    for (int bit = top; bit >= SMP_LOW_BITS; --bit) {
         const uint32_t cand = ans | (1u << bit);
         int c = 0;
 #pragma unroll
         for (int j = 0; j < PER; ++j) c += __popcll(__ballot(kv[j] >= cand));
         if (c >= r) ans = cand;
     }
+    if (!diff) ans = hi & ~((1u << SMP_LOW_BITS) - 1u);
     if (lane == 0) thr[tile * TU + wave] = ans;
 }
 
@@ -371,10 +416,15 @@ __global__ __launch_bounds__(SMP_WAVES *WAVE, 8) void sample_threshold_kernel(
 // list of a user tile holds more than FLT_SUB - 4 after a tile, the four
 // lists of each of that tile's users go to the global buffer (one counter
 // reservation per user); the rest goes there at the end.
-constexpr int FLT_LIST_BYTES = 18 * 1024;  // per workgroup; two per SIMD fit in LDS
+// User tiles per filter wave.
+static constexpr int filter_tiles_per_wave(int kc, bool bf16) {
+    return bf16 ? (kc == 4 ? 4 : kc <= 8 ? 2 : 1) : (kc == 8 ? 4 : kc <= 4 ? 2 : 1);
+}
+// List entries per lane and user tile: two filter workgroups per SIMD (8
+// per CU) leave each 20 KB of the CU's 160 KB of LDS; the lists take 18 KB.
 template <int UT>
 constexpr int filter_sub() {
-    return FLT_LIST_BYTES / (UT * WAVE * 8);
+    return 18 * 1024 / (UT * WAVE * 8);
 }
 
 // Raw buffer resource over `bytes` bytes from `base`: a load at an offset
@@ -454,11 +504,22 @@ __global__ __launch_bounds__(64, 2) void filter_kernel(const float *__restrict__
     // one tile's scores: with the item bias as the accumulator's start; every
     // score is written at its list's end and only a passing one moves the
     // end; then the lists that a further tile could overflow are flushed
-    auto tile = [&](int64_t ib, const ItemFrag<KC, BF16> &A, const f32x4 &b) {
-        f32x4 acc[UT];
+    // one tile's scores, with the item bias as the accumulator's start; the
+    // UT products chunk by chunk, so that consecutive MFMAs are independent
+    // (each product's own chunk order is that of tile_mma)
+    auto products = [&](const ItemFrag<KC, BF16> &A, const f32x4 &b, f32x4 (&acc)[UT]) {
 #pragma unroll
-        for (int q = 0; q < UT; ++q) acc[q] = tile_mma(U[q], A, b);
-        if (FAST && ib + TI > iend) {
+        for (int q = 0; q < UT; ++q) acc[q] = b;
+#pragma unroll
+        for (int c = 0; c < KC; ++c)
+#pragma unroll
+            for (int q = 0; q < UT; ++q) acc[q] = tile_mma_chunk(U[q], A, c, acc[q]);
+    };
+    // every score of tile ib is written at its list's end and only a passing
+    // one moves the end; then the lists that a further tile could overflow
+    // are flushed
+    auto append = [&](int64_t ib, f32x4 (&acc)[UT], bool whole) {
+        if (!whole && ib + TI > iend) {
             // rows past the split read as zeros: no score there
             const int64_t left = iend - ib;
 #pragma unroll
@@ -468,18 +529,19 @@ __global__ __launch_bounds__(64, 2) void filter_kernel(const float *__restrict__
                     if (4 * grp + rr >= left) acc[q][rr] = __builtin_nanf("");
         }
         const uint32_t off = (uint32_t)(ib - ibeg) + 4u * (uint32_t)grp;
-        bool full = false;
+        // the UT lists advance side by side (independent chains)
 #pragma unroll
-        for (int q = 0; q < UT; ++q) {
+        for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
+            for (int q = 0; q < UT; ++q) {
                 const int e = end[q];
                 lst[e] = __float_as_uint(acc[q][rr]);
                 lst[HALF + e] = off + (uint32_t)rr;
                 end[q] = e + (acc[q][rr] >= tf[q] ? WAVE : 0);
             }
-            full |= end[q] > (q * SUB + SUB - 4) * WAVE + lane;
-        }
+        bool full = false;
+#pragma unroll
+        for (int q = 0; q < UT; ++q) full |= end[q] > (q * SUB + SUB - 4) * WAVE + lane;
         if (__ballot(full)) {
 #pragma unroll
             for (int q = 0; q < UT; ++q)
@@ -508,18 +570,21 @@ __global__ __launch_bounds__(64, 2) void filter_kernel(const float *__restrict__
             }
             b = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rb, 16u * (uint32_t)grp, 0, 0));
         };
-        // two tiles per trip, each loaded one tile ahead into the buffer the
-        // other does not use
+        // each tile's rows are loaded one tile ahead of its products; two
+        // buffers alternate
         ItemFrag<KC, BF16> A0, A1;
         f32x4 b0, b1;
+        f32x4 acc[UT];
         load(ibeg, A0, b0);
         for (int64_t ib = ibeg;;) {
             load(ib + TI, A1, b1);
-            tile(ib, A0, b0);
+            products(A0, b0, acc);
+            append(ib, acc, ib + TI <= iend);
             ib += TI;
             if (ib >= iend) break;
             load(ib + TI, A0, b0);
-            tile(ib, A1, b1);
+            products(A1, b1, acc);
+            append(ib, acc, ib + TI <= iend);
             ib += TI;
             if (ib >= iend) break;
         }
@@ -546,7 +611,9 @@ __global__ __launch_bounds__(64, 2) void filter_kernel(const float *__restrict__
             const int64_t inext = ib + TI + ucol;
             An.load(Qf, Qb, inext, inext < iend, k, kb, grp);
             if (ib + TI < iend) load_bias(ib + TI, bn);
-            tile(ib, A, b);
+            f32x4 acc[UT];
+            products(A, b, acc);
+            append(ib, acc, false);
             A = An;
             b = bn;
         }
@@ -556,9 +623,6 @@ __global__ __launch_bounds__(64, 2) void filter_kernel(const float *__restrict__
         if (q < nt) flush(q);
 }
 
-static constexpr int filter_tiles_per_wave(int kc, bool bf16) {
-    return bf16 ? (kc == 4 ? 4 : kc <= 8 ? 2 : 1) : (kc == 8 ? 4 : kc <= 4 ? 2 : 1);
-}
 // The latent chunk count the pass kernels are instantiated for.
 static int dispatch_kc(int kc) { return kc <= 2 ? kc : kc <= 4 ? 4 : kc <= 8 ? 8 : 16; }
 
@@ -588,17 +652,6 @@ static_assert(FIN_BINS == 4 * WAVE, "four bins per lane");
 __device__ __forceinline__ void wave_lds_fence() {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
-}
-
-__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) v = min(v, (uint32_t)__shfl_xor((int)v, off, WAVE));
-    return v;
-}
-__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
-#pragma unroll
-    for (int off = 1; off < WAVE; off <<= 1) v = max(v, (uint32_t)__shfl_xor((int)v, off, WAVE));
-    return v;
 }
 
 // The histogram cut of one user's candidates by one wave: every key that

@@ -325,7 +325,7 @@ bmf_status bmf_topk_dev(bmf_ctx *c, const int32_t *users, int64_t nu, int32_t K,
  * is a fixed array of 64 MiB that the library holds on every device it
  * runs on until the process ends; no device memory is allocated or freed.
  * A request whose workspace exceeds 64 MiB (at K = 100 about 4,200 users
- * at n = 27,000 and k = 64, about 2,300 at n = 100,000 and k = 128) fails
+ * at n = 27,000 and k = 64, about 1,800 at n = 100,000 and k = 128) fails
  * with BMF_E_NOMEM and changes nothing: split it.  Precisions 1 and 2
  * also need the BF16 item table's memory, which the first BF16 call that
  * may allocate (bmf_topk_bf16, bmf_topk_dev, bmf_server_create) makes:

@@ -638,7 +638,7 @@ static int dispatch_kc(int kc) { return kc <= 2 ? kc : kc <= 4 ? 4 : kc <= 8 ? 8
 // reads its candidates from the global buffer once per phase (the reads
 // after the first hit in the caches) and needs no workgroup barrier.
 constexpr int FIN_WG = WAVE;
-constexpr int CAPG_MAX = 4096;
+constexpr int CAPG_MAX = 8192;
 constexpr int FIN_BINS = 256;
 constexpr int FIN_KEEP = 1024;  // >= the largest `need` (1008)
 // LDS for the kept keys: 512 when need <= FIN_KEEP_SMALL_NEED (room for the
@@ -1278,11 +1278,19 @@ TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
     } else {
         T.s = SAMPLE_MAX;
         T.r = std::min(T.s, sample_rank((double)need * T.s / (double)n, 1e-6));
-        // candidates expected above the r-th best of the sample: r / (s + 1)
-        // of the items; three times that plus slack makes an overflow (which
-        // falls back to the full selection) rarer than about 1e-6
+        // the fraction of the items above the r-th best of s sampled ones is
+        // Beta(r, s - r + 1) distributed, about Gamma(r) / (s + 1): r / (s + 1)
+        // on average.  The buffer holds three times the mean plus slack, and
+        // at least the Gamma(r) quantile of 1 - 1e-9 (Wilson-Hilferty, z = 6)
+        // plus slack, so that an overflow (which falls back to the full
+        // selection, one wave sweeping every item) stays rarer than about
+        // 1e-9 per user when r is small
         const double expect = (double)T.r / (T.s + 1) * (double)n;
-        T.capg = std::min(CAPG_MAX, round_up((int)std::min(3.0 * expect + 128.0, (double)CAPG_MAX), 64));
+        const double c9 = 1.0 / (9.0 * T.r);
+        const double wh = 1.0 - c9 + 6.0 * std::sqrt(c9);
+        const double tail = (double)T.r * wh * wh * wh / (T.s + 1) * (double)n + 64.0;
+        const double want = std::max(3.0 * expect + 128.0, tail);
+        T.capg = std::min(CAPG_MAX, round_up((int)std::min(want, (double)CAPG_MAX), 64));
         T.capg = std::max(T.capg, std::min(CAPG_MAX, round_up(need + 64, 64)));
     }
     // item splits for the filter: enough workgroups to fill the chip, and a

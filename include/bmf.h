@@ -482,6 +482,19 @@ bmf_status bmf_debug_block_plan(int64_t n, const int32_t *u_local, const int32_t
                                 int32_t cb, int32_t slots, int32_t chunk, int64_t max_steps, int64_t *n_steps,
                                 uint32_t *out);
 
+/* Host-only: the plan a top-K request of nu users over n items with k
+ * factors gets (bmf_topk_dev and the server make the same one; no device
+ * needed).  out[7] receives: the number s of sampled items the threshold
+ * pass scores (0: no threshold, every item is a candidate), the rank r of
+ * the sampled score taken as the threshold (the smallest r for which fewer
+ * than `need` items reach the r-th best of s sampled ones with probability
+ * at most 1e-6, by the Poisson approximation), the candidates per user the
+ * buffer holds, `need` (K, or the BF16 candidate count for precision 1),
+ * the filter's item splits, the items per split, and the request's
+ * workspace bytes.  Arguments as for bmf_topk_dev; BMF_E_INVAL otherwise. */
+bmf_status bmf_debug_topk_plan(int64_t n, int32_t k, int64_t nu, int32_t K, int32_t precision, int32_t Kc,
+                               int64_t *out);
+
 /* Host-only: the dependency depth of a block's ratings u[x], i[x] (x < n,
  * in processing order, ids >= 0): the length of the longest chain of
  * ratings, each sharing its user or its item with the one before it.

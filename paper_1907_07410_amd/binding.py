@@ -78,6 +78,7 @@ def _load():
         "bmf_chain_depth": ([i64, p, p, p], i32),
         "bmf_debug_chain_floor": ([i32, i32, p], i32),
         "bmf_debug_block_plan": ([i64, p, p, p, i32, i32, i32, i64, p, p], i32),
+        "bmf_debug_topk_plan": ([i64, i32, i64, i32, i32, i32, p], i32),
         "bmf_stratum_order": ([i32, C.c_uint64, i32, i32, p], i32),
         "bmf_batch_create": ([i32, p, p, i32, p, pp], i32),
         "bmf_batch_destroy": ([p], None),
@@ -514,6 +515,16 @@ def block_plan(u_local, i_local, r, cb: int, slots: int, chunk: int) -> np.ndarr
     if st != 0:
         raise BmfError(st, lib.bmf_last_error(None).decode())
     return out
+
+
+def topk_plan(n: int, k: int, nu: int, K: int, precision: int = 0, Kc: int = 0) -> dict:
+    """The plan a top-K request gets (see bmf_debug_topk_plan; host only)."""
+    out = np.zeros(7, dtype=np.int64)
+    st = lib.bmf_debug_topk_plan(n, k, nu, K, precision, Kc, _ptr(out))
+    if st != 0:
+        raise BmfError(st, "bmf_debug_topk_plan")
+    keys = ("samples", "rank", "capacity", "need", "splits", "per_split", "workspace_bytes")
+    return {key: int(v) for key, v in zip(keys, out)}
 
 
 def chain_depth(u, i) -> int:

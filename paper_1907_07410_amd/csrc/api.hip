@@ -626,6 +626,28 @@ bmf_status bmf_sgd_timing(bmf_ctx *c, double *ms, int64_t *launches, int32_t res
     });
 }
 
+bmf_status bmf_debug_topk_plan(int64_t n, int32_t k, int64_t nu, int32_t K, int32_t precision, int32_t Kc,
+                               int64_t *out) {
+    if (!out || n < 1 || k < 1 || k > 256 || nu < 1 || K < 1 || K > 512 || precision < 0 || precision > 2 ||
+        (precision == 1 && Kc != 0 && (Kc < K || Kc > 1008)))
+        return BMF_E_INVAL;
+    try {
+        const bmf::TopkPlan T = bmf::topk_plan(n, k, nu, K, precision, Kc);
+        out[0] = T.s;
+        out[1] = T.r;
+        out[2] = T.capg;
+        out[3] = T.Ksel;
+        out[4] = T.S;
+        out[5] = T.per_split;
+        out[6] = (int64_t)T.total;
+        return BMF_OK;
+    } catch (const bmf::Error &e) {
+        return e.code;
+    } catch (...) {
+        return BMF_E_NOMEM;
+    }
+}
+
 bmf_status bmf_debug_block_plan(int64_t n, const int32_t *u_local, const int32_t *i_local, const float *r,
                                 int32_t cb, int32_t slots, int32_t chunk, int64_t max_steps, int64_t *n_steps,
                                 uint32_t *out) {

@@ -320,6 +320,8 @@ struct TopkPlan {
            total = 0;
 };
 TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc);
+// The same plan from the item count and factor count alone (host only).
+TopkPlan topk_plan(int64_t n, int k, int64_t nu, int K, int precision, int Kc);
 // BF16 candidates per user for a top-K request: Kc when given (at least K),
 // else K + max(16, K / 2).
 inline int topk_candidates(int K, int Kc) { return Kc > 0 ? (Kc > K ? Kc : K) : K + (K / 2 > 16 ? K / 2 : 16); }

@@ -1254,6 +1254,10 @@ void ensure_bf16_items(Model &M, bool may_alloc) {
 }
 
 TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
+    return topk_plan(M.n, M.k, nu, K, precision, Kc);
+}
+
+TopkPlan topk_plan(int64_t n, int k, int64_t nu, int K, int precision, int Kc) {
     TopkPlan T;
     T.nu = nu;
     T.K = K;
@@ -1265,10 +1269,9 @@ TopkPlan topk_plan(const Model &M, int64_t nu, int K, int precision, int Kc) {
         T.prune = (e && e[0] == '0' && e[1] == 0) ? 0 : 1;
     }
     if (K < 1 || T.Ksel > 1008) BMF_FAIL(BMF_E_INVAL, "top-K needs 1 <= K and at most 1008 candidates per user");
-    T.kp = round_up(M.k, 16);
-    T.kb = round_up(M.k, 32);
+    T.kp = round_up(k, 16);
+    T.kb = round_up(k, 32);
     T.nu_pad = (nu + TU - 1) / TU * TU;
-    const int64_t n = M.n;
     const int need = T.Ksel;
     if (need >= n || n <= SAMPLE_MAX) {
         // every item is a candidate

@@ -6,12 +6,14 @@
 // method, so it runs on MFMA and is never stored; the work that remains is
 // selection.  Three passes per request:
 //  1. threshold: the r-th best of each user's scores against a fixed sample
-//     of s = 1024 evenly spaced item ids, r chosen so that the chance that
-//     fewer than the needed number of items reach it is below 1e-6 (no
-//     threshold when n <= 1024: every item is a candidate);
+//     of s = 1024 evenly spaced item ids (rounded down in its last 8 key
+//     bits), r chosen so that the chance that fewer than the needed number
+//     of items reach it is below 1e-6 (no threshold when n <= 1024: every
+//     item is a candidate);
 //  2. filter: the full user x item contraction, split over the item range
-//     across workgroups; every score at or above the user's threshold is
-//     appended to the user's candidate buffer in global memory;
+//     across workgroups; every score at or above the user's threshold goes
+//     through a per-lane list in LDS to the user's candidate buffer in
+//     global memory, sized so that it overflows for about 1 user in 1e9;
 //  3. finish: one wave per user keeps the candidates that can be among the
 //     best (a histogram cut), sorts them and keeps the best.
 // A user whose buffer got fewer than the needed candidates (or overflowed,
@@ -29,6 +31,8 @@
 //              rescore are one kernel, which rescores only the candidates
 //              that a bound on the BF16 rounding leaves able to reach the
 //              FP32 top K (the answer equals rescoring all Kc).
+//   BF16 only: the BF16 path's ranking with its BF16 scores, K candidates
+//              and no rescore.
 //
 // The latent index order inside an MFMA tile is fixed and independent of
 // the users sharing the tile, and a user's threshold and candidates depend

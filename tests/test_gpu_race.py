@@ -129,3 +129,27 @@ def test_check_refuses_without_resident_ratings(B):
         G.check_disjoint()
     assert ex.value.status == B.BMF_E_STATE
     G.close()
+
+
+def test_paper_grid_is_disjoint(B):
+    """The paper's 3072 x 3072 grid on MovieLens-1M-sized data (2 users x 2
+    items per block, most blocks empty or nearly): zero on the epochs'
+    schedule, and a stratum that puts two columns a user rated on that
+    user's block row is caught."""
+    m, n, b = 6040, 3900, 3072
+    rat = synth.random_coo(m, n, 1_000_000, seed=31, dup=True)
+    G = B.Model(m, n, 13, b)
+    G.load_ratings(rat.u, rat.i, rat.r)
+    assert G.check_disjoint() == 0
+    assert G.check_disjoint(latin(b)) == 0
+    rb, cb = -(-m // b), -(-n // b)
+    u0 = int(rat.u[0])
+    cols = np.unique(rat.i[rat.u == u0] // cb)
+    assert cols.size >= 2
+    pairing = latin(b)
+    pairing[0, cols[0]] = u0 // rb
+    pairing[0, cols[1]] = u0 // rb
+    got = G.check_disjoint(pairing)
+    log("paper grid broken pairing", got)
+    assert got > 0
+    G.close()

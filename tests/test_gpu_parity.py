@@ -464,6 +464,31 @@ def test_topk_bf16_only_scores_within_the_rounding_bound(B, orc, k, n, nu, K):
     G.close()
 
 
+def test_topk_bf16_only_short_lists_and_ties(B):
+    """Precision 2 with K > n: every item, in BF16 score order, then item -1
+    and score -inf; equal scores (equal rows and biases) go to the smaller
+    item id."""
+    import torch
+    k, n, m, K = 32, 40, 3, 50
+    Q = np.tile(np.linspace(-1, 1, k, dtype=np.float32), (n, 1))
+    bi = np.zeros(n, np.float32)
+    bi[7] = 0.5
+    G = B.Model(m, n, k, 2)
+    G.set_factors(np.ones((m, k), np.float32), Q, np.zeros(m, np.float32), bi, 0.0)
+    du = torch.tensor([0, 2], dtype=torch.int32, device="cuda")
+    it = torch.zeros((2, K), dtype=torch.int32, device="cuda")
+    sc = torch.zeros((2, K), dtype=torch.float32, device="cuda")
+    G.topk_dev(du, K, 2, 0, it, sc)
+    G.synchronize()
+    items, scores = it.cpu().numpy(), sc.cpu().numpy()
+    want = [7] + [x for x in range(n) if x != 7]
+    for row in range(2):
+        assert items[row][:n].tolist() == want
+        assert np.all(items[row][n:] == -1) and np.all(np.isneginf(scores[row][n:]))
+        assert np.all(np.diff(scores[row][:n]) <= 0)
+    G.close()
+
+
 @pytest.mark.parametrize("scale,k,Kc", [(0.02, 128, 0), (0.3, 128, 0), (0.05, 64, 300), (0.02, 13, 0)])
 def test_topk_bf16_candidate_drop_changes_nothing(B, monkeypatch, scale, k, Kc):
     """The BF16 path drops candidates whose BF16 score lies more than twice

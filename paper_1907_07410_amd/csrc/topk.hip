@@ -505,9 +505,6 @@ __global__ __launch_bounds__(64, 2) void filter_kernel(const float *__restrict__
         }
         end[q] = first;
     };
-    // one tile's scores: with the item bias as the accumulator's start; every
-    // score is written at its list's end and only a passing one moves the
-    // end; then the lists that a further tile could overflow are flushed
     // one tile's scores, with the item bias as the accumulator's start; the
     // UT products chunk by chunk, so that consecutive MFMAs are independent
     // (each product's own chunk order is that of tile_mma)

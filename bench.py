@@ -41,8 +41,8 @@ MFMA_PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}  # MI355X dense matrix peaks
 # that makes the same counter read a plain copy kernel's known bytes; valid
 # for the kernel sources with this sha1 and reported as null once they
 # change.
-SGD_TRAFFIC = {"large": {"sources_sha1": "74d1c743586dfc652929386b49938ffb9f600e93",
-                         "fetch_bytes": 61719.5 * 1024 * 2.0, "write_bytes": 111948.1 * 1024 * 1.0}}
+SGD_TRAFFIC = {"large": {"sources_sha1": "cf312bb15e1872c0a1b5821fe1b23c33324da22a",
+                         "fetch_bytes": 61719.5 * 1024 * 2.0, "write_bytes": 111948.0 * 1024 * 1.0}}
 SGD_SOURCES = ["paper_1907_07410_amd/csrc/sgd.hip", "paper_1907_07410_amd/csrc/plan.hip",
                "paper_1907_07410_amd/csrc/plan.h", "paper_1907_07410_amd/csrc/wave.h"]
 
